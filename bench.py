@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Benchmark: exact directed-pattern counting on one MI355X.
+
+Workload (default): R-MAT scale 16 (65,536 nodes, ~955K arcs after removing
+repeats and loops, (a,b,c,d) = (.57,.19,.19,.05), seed 0), uint32 out+in CSR
+resident in HBM, and four patterns: feed-forward triangle, directed 3-cycle,
+bi-fan, directed 4-cycle.  One step counts all four with their reduced plans
+in one persistent launch, replayed as a HIP graph.  The same step is also
+timed as plain per-pattern launches and with unreduced plans.
+
+Prints one JSON line (see the repository's benchmark contract).  Only the
+`cpu_baseline` leg calls the oracle, on a bounded root sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("embeddings counted/sec + adjacency elems intersected/s (HBM GB/s %), "
+          "batched vs plain")
+HBM_PEAK_GBPS = 8000.0
+PATTERNS = ["ffl", "c3", "bifan", "c4"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def lib_hash() -> str:
+    from paper_2404_11105_amd._lib import LIB_PATH
+    h = hashlib.sha256()
+    with open(LIB_PATH, "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def timed_steps(counter, stream, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        counter.run(stream)
+    stream.synchronize()
+    kms = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        counter.run(stream)
+        stream.synchronize()
+        if counter.events is not None:
+            kms.append(counter.kernel_ms())
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps * 1e3
+    return wall, (sum(kms) / len(kms) if kms else None)
+
+
+def timed_plain(counters, stream, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        for c in counters:
+            c.run(stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for c in counters:
+            c.run(stream)
+        stream.synchronize()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps * 1e3
+
+
+def cpu_baseline(g, pats, target_s=4.0):
+    """The oracle as it stands, on a seeded uniform sample of roots."""
+    import numpy as np
+
+    import oracle
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    threads = max(1, min(16, cores))
+    rng = np.random.default_rng(12345)
+    total_c, total_t, parts = 0, 0.0, []
+    for p in pats:
+        frac = 0.002
+        while True:
+            k = max(1, int(frac * g.n))
+            roots = np.sort(rng.choice(g.n, size=k, replace=False)).astype(np.uint32)
+            t = time.perf_counter()
+            c = oracle.count(g, p, roots=roots, threads=threads)
+            dt = time.perf_counter() - t
+            if dt >= target_s / 4 or frac >= 1.0:
+                break
+            frac = min(1.0, frac * max(2.0, min(50.0, target_s / max(dt, 1e-3))))
+        total_c += c
+        total_t += dt
+        parts.append(f"{p.name}:{k}/{g.n} roots")
+    return {"value": total_c / total_t, "unit": "embeddings/s", "cores": threads, "kind": "oracle",
+            "sample": "seeded uniform root samples per pattern (" + ", ".join(parts) +
+                      f"), {total_c} embeddings in {total_t:.2f} s"}
+
+
+def traffic_from_profile(n_launch_plans):
+    path = os.path.join(ROOT, "profiles", "count_kernel_rmat16_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        if rec.get("lib_sha256_16") != lib_hash():
+            return None
+        return rec.get("hbm_bytes_per_launch")
+    except Exception:
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip plain/unreduced timings")
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--split", type=int, default=0)
+    ap.add_argument("--cap", type=int, default=0)
+    ap.add_argument("--waves-per-cu", type=int, default=0)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(roots would shard across GPUs with one final 128-bit sum; not built).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import xmgen
+    from paper_2404_11105_amd import Counter, Graph, Plan
+
+    torch.cuda.set_device(0)
+    log("[bench] generating R-MAT scale 16")
+    g = xmgen.rmat(16, seed=0)
+    pats = [xmgen.named(n) for n in PATTERNS]
+    G = Graph(g)
+    tune = dict(chunk=args.chunk, split=args.split, cap=args.cap, waves_per_cu=args.waves_per_cu)
+    red = [Plan(p, reduced=True, graph=G) for p in pats]
+    unred = [Plan(p, reduced=False, graph=G) for p in pats]
+    s = torch.cuda.Stream()
+
+    # untimed work statistics of the batched reduced launch
+    log("[bench] stats pass")
+    cs = Counter(G, red, stats=True, **tune)
+    cs.run(s)
+    s.synchronize()
+    counts_stats, _ = cs.results()
+    st = cs.stats_list()
+    E = sum(x["elements"] for x in st)
+    F = sum(x["fetches"] for x in st)
+    B_alg = 4 * E + 8 * F + 8 * g.n * len(pats)
+
+    log("[bench] batched reduced (HIP graph)")
+    cb = Counter(G, red, kernel_events=True, stream=s, **tune)
+    cb.capture(s)
+    ms_step, kern_ms = timed_steps(cb, s, args.steps, args.warmup)
+    counts, status = cb.results()
+    assert status == [0] * len(pats), status
+    assert counts == counts_stats
+
+    extras = {}
+    if not args.no_extras:
+        log("[bench] plain per-pattern launches")
+        plain = [Counter(G, [p], **tune) for p in red]
+        ms_plain = timed_plain(plain, s, args.steps, args.warmup)
+        assert [c.results()[0][0] for c in plain] == counts
+        log("[bench] batched unreduced")
+        cu = Counter(G, unred, kernel_events=True, stream=s, **tune)
+        cu.capture(s)
+        ms_unred, kern_unred = timed_steps(cu, s, max(3, args.steps // 4), 1)
+        assert cu.results()[0] == counts
+        cus = Counter(G, unred, stats=True, **tune)
+        cus.run(s)
+        s.synchronize()
+        E_un = sum(x["elements"] for x in cus.stats_list())
+        extras = {"plain_ms_per_step": round(ms_plain, 4),
+                  "batched_vs_plain_speedup": round(ms_plain / ms_step, 3),
+                  "unreduced_ms_per_step": round(ms_unred, 4),
+                  "unreduced_kernel_ms": round(kern_unred, 4),
+                  "reduced_vs_unreduced_speedup": round(ms_unred / ms_step, 3),
+                  "unreduced_elements": E_un}
+
+    gold_ok = None
+    gpath = os.path.join(ROOT, "tests", "golden", "rmat16.json")
+    if os.path.exists(gpath):
+        gold = json.load(open(gpath))["counts"]
+        gold_ok = counts == [int(gold[n]) for n in PATTERNS]
+
+    total = sum(counts)
+    value = total / (ms_step / 1e3)
+    achieved = B_alg / (kern_ms / 1e3) / 1e9
+    traffic = traffic_from_profile(len(pats))
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] oracle cpu baseline")
+        cpu = cpu_baseline(g, pats)
+
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "embeddings/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "rmat16_ffl_c3_bifan_c4_reduced_batched",
+                   "graph": "R-MAT scale 16, edge factor 16, (.57,.19,.19,.05), seed 0",
+                   "n": g.n, "m": g.m, "patterns": PATTERNS, "plan": "reduced",
+                   "launch": "one persistent launch for 4 patterns, HIP graph replay",
+                   "parallelism": "1 GPU"},
+        "counts": [str(c) for c in counts],
+        "counts_match_oracle": gold_ok,
+        "kernel_ms": round(kern_ms, 4),
+        "elements_intersected": E,
+        "list_fetches": F,
+        "elements_per_s": E / (kern_ms / 1e3),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic},
+        "cpu_baseline": cpu,
+        **extras,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

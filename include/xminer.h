@@ -1,0 +1,206 @@
+/*
+ * xminer.h — C ABI of the MI355X (gfx950) exact directed-pattern counter.
+ *
+ * The library counts the embeddings of a small directed pattern graph in a
+ * large directed data graph: the number of injective maps phi from pattern
+ * vertices to data nodes such that every pattern arc (u, w) lands on a data
+ * arc (phi(u), phi(w)), oriented the same (the paper, section 2: Definitions
+ * 2.1 Digraph and 2.2 Pattern Graph, with constraint set C = vertices u
+ * edges; counting by multiplying candidate-set sizes, section 5.3).  Matches
+ * are non-induced and labelled: they are not divided by the pattern's
+ * automorphism count.
+ *
+ * The work runs in three calls:
+ *   xm_load_graph  registers a resident data graph (uint32 out-CSR + in-CSR);
+ *   xm_plan        reduces the pattern and emits a level-by-level plan on the
+ *                  host (section 4: inclusion sets, Theorem 2.1, minimum
+ *                  constraint cover, Algorithm 1; section 5.1 plan generation);
+ *   xm_count       executes one or many plans on the GPU (Algorithm 2 plan
+ *                  execution, section 5.2 intermediate-result reuse, section
+ *                  5.3 result generation by product) and writes exact counts.
+ *
+ * Conventions
+ *   - Every call returns int: XM_OK (0) or a negative xm_status.  Argument
+ *     errors are found on the host before anything is enqueued and leave no
+ *     side effects.  xm_last_error() gives a message for the calling thread.
+ *   - Ownership: the library never frees caller memory.  It owns xm_graph_t,
+ *     xm_plan_t and xm_exec_t objects, which the caller frees with xm_free_*.
+ *   - Streams: void* hip_stream is a hipStream_t (NULL = the null stream).
+ *     xm_count is asynchronous on that stream.
+ *   - Device: all device pointers must belong to the device that was current
+ *     when the graph was loaded.
+ */
+#ifndef XMINER_H
+#define XMINER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define XM_MAX_K 7 /* largest pattern (vertices) */
+
+typedef enum xm_status {
+    XM_OK = 0,
+    XM_ERR_INVALID = -1,   /* bad argument: NULL, size out of range, unknown flag */
+    XM_ERR_PATTERN = -2,   /* pattern rejected: k outside 2..7, arc endpoint >= k,
+                              self-loop arc, no arcs, not weakly connected */
+    XM_ERR_OOM = -3,       /* host or device allocation failed */
+    XM_ERR_HIP = -4,       /* a HIP runtime call failed (see xm_last_error) */
+    XM_ERR_OVERFLOW = -5,  /* status only: a total exceeded 2^128 - 1 */
+    XM_ERR_WORKSPACE = -6, /* workspace NULL or smaller than xm_workspace_size */
+    XM_ERR_CANCELLED = -7, /* status only: stopped through the cancel flag */
+    XM_ERR_GRAPH = -8      /* graph failed validation (XM_VALIDATE) */
+} xm_status;
+
+typedef struct xm_graph_s xm_graph_t; /* immutable after load; shareable between threads */
+typedef struct xm_plan_s xm_plan_t; /* immutable; host-side plan + compact descriptor */
+typedef struct xm_exec_s xm_exec_t; /* an instantiated HIP graph of one xm_count call */
+
+/* ----------------------------------------------------------------------------
+ * Graph residency (Definition 2.1; the paper keeps the data graph resident
+ * and excludes loading from timing, section 6.1).
+ *
+ * n nodes 0..n-1 (1 <= n < 2^32 - 1), m arcs (m < 2^32).
+ * out_off[n+1], out_adj[m]: out-CSR, each list sorted ascending, no repeats,
+ *                           no self-loops.
+ * in_off[n+1],  in_adj[m]:  in-CSR, the transpose of the out-CSR, same rules.
+ * flags:
+ *   XM_MEM_DEVICE  the four arrays are device pointers; the library BORROWS
+ *                  them: the caller keeps them alive and unchanged until
+ *                  xm_free_graph.
+ *   XM_MEM_HOST    the four arrays are host pointers; the library copies them
+ *                  to device memory it owns.
+ *   XM_VALIDATE    check the rules above on the host (copies device arrays
+ *                  back when XM_MEM_DEVICE); failure returns XM_ERR_GRAPH.
+ * Exactly one of XM_MEM_DEVICE / XM_MEM_HOST must be set.  The call also
+ * builds per-node degree pairs and a hub list on the device (library-owned),
+ * and synchronises hip_stream before returning.
+ * ------------------------------------------------------------------------- */
+#define XM_MEM_DEVICE 0x1u
+#define XM_MEM_HOST 0x2u
+#define XM_VALIDATE 0x4u
+int xm_load_graph(uint32_t n, uint32_t m,
+                  const uint32_t* out_off, const uint32_t* out_adj,
+                  const uint32_t* in_off, const uint32_t* in_adj,
+                  uint32_t flags, void* hip_stream, xm_graph_t** out);
+int xm_free_graph(xm_graph_t* g);
+/* Graph facts: n, m, max out-degree, max in-degree (any pointer may be NULL). */
+int xm_graph_info(const xm_graph_t* g, uint32_t* n, uint32_t* m,
+                  uint32_t* max_out, uint32_t* max_in);
+
+/* ----------------------------------------------------------------------------
+ * Planning (section 4.1 constraint inclusion; section 4.2 / Algorithm 1
+ * reduction and minimum constraint cover; section 5.1 plan generation).
+ *
+ * k pattern vertices (2..XM_MAX_K), n_arcs arcs given as k-bounded byte pairs
+ * arcs[2*i] -> arcs[2*i+1].  Repeated arcs are ignored; a bidirected edge is
+ * two arcs.  flags: exactly one of
+ *   XM_PLAN_REDUCED    pattern-reduced plan: sibling vertices share one
+ *                      fetched candidate set, included constraints are
+ *                      materialised from the including one, trailing
+ *                      independent vertices are counted by product;
+ *   XM_PLAN_UNREDUCED  every level materialises its own constraints from the
+ *                      data graph; only the last vertex is counted, not
+ *                      enumerated;
+ * optionally OR'ed with XM_PLAN_ROOT(v) to force pattern vertex v as the
+ * plan's start vertex (needed for root-subset counting).
+ * g (nullable) supplies degree statistics used as cover weights; with g NULL
+ * the plan uses unit weights.  No device work is done.
+ * ------------------------------------------------------------------------- */
+#define XM_PLAN_REDUCED 0x1u
+#define XM_PLAN_UNREDUCED 0x2u
+#define XM_PLAN_ROOT(v) ((((uint32_t)(v)) + 1u) << 8)
+int xm_plan(uint32_t k, uint32_t n_arcs, const uint8_t* arcs, uint32_t flags,
+            const xm_graph_t* g, xm_plan_t** out);
+/* JSON description: vertex order, levels and their constraints, reuse
+ * sources, leaf groups and product terms, inclusion groups, the exact
+ * minimum constraint cover and Algorithm 1's greedy cover.  Writes at most
+ * cap bytes including the terminating NUL; *needed (nullable) receives the
+ * full length + 1.  Returns XM_ERR_INVALID if cap is too small. */
+int xm_plan_describe(const xm_plan_t* p, char* json, size_t cap, size_t* needed);
+/* The pattern vertex the plan starts from (images of it are the roots). */
+int xm_plan_root_vertex(const xm_plan_t* p);
+int xm_free_plan(xm_plan_t* p);
+
+/* ----------------------------------------------------------------------------
+ * Counting (Algorithm 2; sections 5.2-5.3).
+ *
+ * Counts every plan in plans[0..n_plans) against g in ONE persistent kernel
+ * launch (batched form) on hip_stream.  n_plans = 1 is the plain form.
+ *
+ * counts_dev: caller device buffer of 2*n_plans uint64: (lo, hi) of the
+ *             unsigned 128-bit count of plan i at [2i], [2i+1].
+ * status_dev: caller device buffer of n_plans int32: XM_OK, XM_ERR_OVERFLOW
+ *             (total exceeded 2^128 - 1; counts then wrap) or
+ *             XM_ERR_CANCELLED.
+ * workspace:  caller device buffer of at least xm_workspace_size(...) bytes,
+ *             same n_plans, plans and opts.  Its contents are scratch; the
+ *             call initialises what it needs on the stream.  Calls that share
+ *             one workspace must not overlap in time.
+ * opts (nullable): see xm_count_opts.  Fields left 0 take defaults.
+ * Returns after enqueueing; results are ready when hip_stream completes.
+ * ------------------------------------------------------------------------- */
+#define XM_COUNT_STATS 0x1u /* also write per-plan work statistics (slower) */
+
+typedef struct xm_count_opts {
+    uint32_t struct_size;   /* sizeof(xm_count_opts) */
+    uint32_t flags;         /* XM_COUNT_STATS */
+    uint32_t chunk;         /* roots taken per work grab (default 8) */
+    uint32_t split;         /* first-level candidate lists longer than this are
+                               split into stealable sub-ranges (default 512) */
+    uint32_t cap;           /* per-level candidate buffer entries (default 4096,
+                               at least split) */
+    uint32_t waves_per_cu;  /* resident waves per compute unit (default 16) */
+    /* root subset: device array of n_roots node ids (< n, distinct); when
+       non-NULL only these nodes are tried as images of the plan's start
+       vertex (xm_plan_root_vertex).  Counts are then exact partial sums. */
+    const uint32_t* roots_dev;
+    uint32_t n_roots;
+    uint32_t reserved0;
+    /* cancel flag: device int32; when it becomes nonzero, waves stop taking
+       new work and the status of unfinished plans is XM_ERR_CANCELLED. */
+    const int32_t* cancel_dev;
+    /* XM_COUNT_STATS: device buffer of 4*n_plans uint64 per plan:
+       [0] adjacency elements intersected (base list + every probed list, full
+       lengths), [1] list fetches, [2] partial matches materialised,
+       [3] root tasks. */
+    uint64_t* stats_dev;
+    /* Profiling (nullable hipEvent_t): recorded on hip_stream immediately
+       before and after the count kernel itself, so its duration excludes the
+       small set-up and status kernels. */
+    void* ev_kernel_start;
+    void* ev_kernel_stop;
+} xm_count_opts;
+
+size_t xm_workspace_size(const xm_graph_t* g, uint32_t n_plans,
+                         const xm_plan_t* const* plans, const xm_count_opts* opts);
+int xm_count(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* plans,
+             const xm_count_opts* opts, void* workspace, size_t ws_bytes,
+             uint64_t* counts_dev, int32_t* status_dev, void* hip_stream);
+
+/* ----------------------------------------------------------------------------
+ * HIP-graph form of xm_count: records the same launches once (captured on
+ * hip_stream) and instantiates them; xm_exec_launch replays them with the
+ * arguments given at capture (same workspace, counts, status, plans).  The
+ * caller keeps every buffer alive until xm_free_exec.
+ * ------------------------------------------------------------------------- */
+int xm_count_capture(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* plans,
+                     const xm_count_opts* opts, void* workspace, size_t ws_bytes,
+                     uint64_t* counts_dev, int32_t* status_dev, void* hip_stream,
+                     xm_exec_t** out);
+int xm_exec_launch(xm_exec_t* e, void* hip_stream);
+int xm_free_exec(xm_exec_t* e);
+
+const char* xm_strerror(int code);
+const char* xm_last_error(void);
+/* Library version string. */
+const char* xm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XMINER_H */

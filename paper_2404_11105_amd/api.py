@@ -1,0 +1,237 @@
+"""Python binding over the C ABI (argument marshalling only).
+
+    g = Graph(digraph)                       # xm_load_graph (device buffers borrowed)
+    p = Plan(pattern, reduced=True, graph=g) # xm_plan
+    counts = count(g, [p])                   # xm_count -> list of Python ints
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+
+import numpy as np
+
+from . import _lib
+from ._lib import check, lib
+
+
+def _u32_tensor(a, device):
+    import torch
+    arr = np.ascontiguousarray(a, dtype=np.uint32)
+    if arr.size == 0:
+        arr = np.zeros(1, dtype=np.uint32)
+    return torch.from_numpy(arr.view(np.int32)).to(device)
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Graph:
+    """A resident data graph: uint32 out-CSR + in-CSR in device memory.
+
+    The device tensors are owned here and borrowed by the library
+    (XM_MEM_DEVICE) until close().
+    """
+
+    def __init__(self, digraph, device: str = "cuda", validate: bool = False, stream=None):
+        import torch
+        self.n = int(digraph.n)
+        self.m = int(digraph.m)
+        self.device = torch.device(device)
+        self.tensors = [_u32_tensor(x, self.device) for x in
+                        (digraph.out_off, digraph.out_adj, digraph.in_off, digraph.in_adj)]
+        self.nbytes = sum(t.numel() * 4 for t in self.tensors)
+        h = ctypes.c_void_p()
+        flags = _lib.XM_MEM_DEVICE | (_lib.XM_VALIDATE if validate else 0)
+        with torch.cuda.device(self.device):
+            check(lib().xm_load_graph(self.n, self.m, *[ctypes.c_void_p(t.data_ptr()) for t in self.tensors],
+                                      flags, _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def info(self):
+        n, m, mo, mi = (ctypes.c_uint32() for _ in range(4))
+        check(lib().xm_graph_info(self.handle, ctypes.byref(n), ctypes.byref(m),
+                                  ctypes.byref(mo), ctypes.byref(mi)))
+        return {"n": n.value, "m": m.value, "max_out": mo.value, "max_in": mi.value}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().xm_free_graph(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """A counting plan for one pattern (reduced or unreduced)."""
+
+    def __init__(self, pattern, reduced: bool = True, graph: Graph | None = None,
+                 root_vertex: int | None = None):
+        self.pattern = pattern
+        self.reduced = reduced
+        arcs = (ctypes.c_uint8 * max(1, 2 * len(pattern.arcs)))(*pattern.arcs_u8())
+        flags = _lib.XM_PLAN_REDUCED if reduced else _lib.XM_PLAN_UNREDUCED
+        if root_vertex is not None:
+            flags |= _lib.XM_PLAN_ROOT(root_vertex)
+        h = ctypes.c_void_p()
+        check(lib().xm_plan(pattern.k, len(pattern.arcs), arcs, flags,
+                            graph.handle if graph is not None else None, ctypes.byref(h)))
+        self.handle = h
+
+    def describe(self) -> dict:
+        return json.loads(plan_json(self))
+
+    @property
+    def root_vertex(self) -> int:
+        return check(lib().xm_plan_root_vertex(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().xm_free_plan(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan_json(plan: Plan) -> str:
+    need = ctypes.c_size_t()
+    lib().xm_plan_describe(plan.handle, None, 0, ctypes.byref(need))
+    buf = ctypes.create_string_buffer(need.value)
+    check(lib().xm_plan_describe(plan.handle, buf, need.value, None))
+    return buf.value.decode()
+
+
+def describe_plan(pattern, reduced: bool = True) -> dict:
+    return Plan(pattern, reduced).describe()
+
+
+def make_opts(chunk=0, split=0, cap=0, waves_per_cu=0, roots=None, cancel=None, stats=None,
+              events=None):
+    o = _lib.XmCountOpts()
+    o.struct_size = ctypes.sizeof(_lib.XmCountOpts)
+    o.chunk, o.split, o.cap, o.waves_per_cu = chunk, split, cap, waves_per_cu
+    if roots is not None:
+        o.roots_dev = roots.data_ptr()
+        o.n_roots = roots.numel()
+    if cancel is not None:
+        o.cancel_dev = cancel.data_ptr()
+    if stats is not None:
+        o.stats_dev = stats.data_ptr()
+        o.flags |= _lib.XM_COUNT_STATS
+    if events is not None:
+        o.ev_kernel_start = events[0].cuda_event
+        o.ev_kernel_stop = events[1].cuda_event
+    return o
+
+
+class Counter:
+    """One reusable xm_count call: fixed graph, plans and options.
+
+    Owns the workspace, count and status tensors; run() enqueues on a
+    stream, results() waits and converts the (lo, hi) pairs to ints.
+    """
+
+    def __init__(self, graph: Graph, plans, chunk=0, split=0, cap=0, waves_per_cu=0,
+                 roots=None, cancel=None, stats: bool = False, kernel_events: bool = False,
+                 stream=None):
+        import torch
+        self.graph = graph
+        self.plans = list(plans)
+        dev = graph.device
+        self.roots = None
+        if roots is not None:
+            self.roots = _u32_tensor(np.asarray(roots, dtype=np.uint32), dev)
+        self.cancel = cancel
+        self.stats = torch.zeros(4 * len(self.plans), dtype=torch.int64, device=dev) if stats else None
+        self.events = None
+        if kernel_events:
+            # events around the count kernel itself; recording once creates them
+            with torch.cuda.device(dev):
+                s = stream if stream is not None else torch.cuda.current_stream()
+                self.events = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                for ev in self.events:
+                    ev.record(s)
+        self.opts = make_opts(chunk, split, cap, waves_per_cu, self.roots, cancel, self.stats,
+                              self.events)
+        self._parr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        ws = lib().xm_workspace_size(graph.handle, len(self.plans), self._parr, ctypes.byref(self.opts))
+        if ws == 0:
+            check(_lib.XM_ERR_INVALID if lib().xm_last_error() else _lib.XM_ERR_INVALID)
+        self.ws_bytes = int(ws)
+        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.counts = torch.zeros(2 * len(self.plans), dtype=torch.int64, device=dev)
+        self.status = torch.zeros(len(self.plans), dtype=torch.int32, device=dev)
+        self.exec = None
+
+    def _args(self):
+        return (self.graph.handle, len(self.plans), self._parr, ctypes.byref(self.opts),
+                ctypes.c_void_p(self.workspace.data_ptr()), self.ws_bytes,
+                ctypes.c_void_p(self.counts.data_ptr()), ctypes.c_void_p(self.status.data_ptr()))
+
+    def run(self, stream=None):
+        import torch
+        with torch.cuda.device(self.graph.device):
+            if self.exec is not None:
+                check(lib().xm_exec_launch(self.exec, _stream_ptr(stream)))
+            else:
+                check(lib().xm_count(*self._args(), _stream_ptr(stream)))
+
+    def capture(self, stream):
+        """Record this call once as a HIP graph; later run() calls replay it."""
+        import torch
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.graph.device):
+            check(lib().xm_count_capture(*self._args(), _stream_ptr(stream), ctypes.byref(h)))
+        self.exec = h
+
+    def results(self, sync: bool = True):
+        import torch
+        if sync:
+            torch.cuda.synchronize(self.graph.device)
+        c = self.counts.cpu().numpy().view(np.uint64)
+        st = self.status.cpu().numpy()
+        out = [int(c[2 * i]) | (int(c[2 * i + 1]) << 64) for i in range(len(self.plans))]
+        return out, [int(s) for s in st]
+
+    def kernel_ms(self) -> float:
+        """Duration of the last count kernel (call after the stream completed)."""
+        return self.events[0].elapsed_time(self.events[1])
+
+    def stats_list(self):
+        s = self.stats.cpu().numpy().view(np.uint64).reshape(-1, 4)
+        return [dict(elements=int(r[0]), fetches=int(r[1]), partial_matches=int(r[2]),
+                     root_tasks=int(r[3])) for r in s]
+
+    def close(self):
+        if self.exec is not None:
+            lib().xm_free_exec(self.exec)
+            self.exec = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def count(graph: Graph, plans, stream=None, **opts):
+    """Count every plan against graph in one batched launch; returns ints."""
+    c = Counter(graph, plans, **opts)
+    c.run(stream)
+    counts, status = c.results()
+    for s in status:
+        if s != 0:
+            check(s)
+    return counts

@@ -1,0 +1,750 @@
+// count.hip — gfx950 kernels that execute counting plans.
+//
+// Algorithm 2 (plan execution) run by wavefronts.  Each wave is a worker
+// that takes tasks from two device queues: first-level sub-ranges of hub
+// roots (split by the split kernel so that other waves can take them, the
+// work-stealing of Algorithm 2's parallel loop), then chunks of ordinary
+// roots.  A task is explored depth-first, one level buffer per plan level;
+// each buffer holds a window of partial matches, and every expansion is
+// flattened across the window so that the 64 lanes stay busy even when
+// adjacency lists are short (power-law graphs have mostly short lists).
+//
+// Per element of a base list a lane checks, in order: injectivity against
+// the bound nodes (visited marks), the degree thresholds, and membership in
+// every other constraint list (sorted uint32 lists, binary search).  The
+// survivors are compacted with a 64-bit ballot and a popcount.  The leaf
+// group of a plan is counted, not enumerated: with one leaf the count is a
+// popcount sum; with several, each partial match builds a membership
+// histogram in LDS and evaluates the planner's inclusion-exclusion terms in
+// 128-bit integers.  Totals are unsigned 128-bit, kept as (lo, hi) uint64
+// pairs updated with 64-bit atomics and an explicit carry.
+//
+// Nothing here is a dense contraction, so no matrix cores are used; the
+// kernels are bound by memory latency and bandwidth of list reads.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+namespace xm {
+
+static_assert(sizeof(PlanDesc) % 4 == 0, "plan descriptors are copied in 32-bit words");
+
+constexpr uint32_t kSkip = 0xFFFFFFFFu;
+constexpr uint32_t kComplete = 0x80000000u;
+
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint32_t lane_id() {
+    return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+__device__ __forceinline__ uint32_t rank_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+// Make this wave's global and LDS writes visible to its other lanes.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint32_t scan_incl(uint32_t v, uint32_t lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, 64);
+        if (lane >= (uint32_t)d) v += t;
+    }
+    return v;
+}
+
+// Sorted-list membership: branchless search for the last element <= x.
+__device__ __forceinline__ bool contains(const uint32_t* __restrict__ a, uint32_t len, uint32_t x) {
+    if (len == 0) return false;
+    uint32_t base = 0, n = len;
+    while (n > 1) {
+        uint32_t h = n >> 1;
+        base = (a[base + h] <= x) ? base + h : base;
+        n -= h;
+    }
+    return a[base] == x;
+}
+
+__device__ __forceinline__ const uint32_t* adj_of(const DevGraph& g, uint32_t dir) {
+    return dir ? g.in_adj : g.out_adj;
+}
+__device__ __forceinline__ const uint32_t* off_of(const DevGraph& g, uint32_t dir) {
+    return dir ? g.in_off : g.out_off;
+}
+
+// Unsigned 128-bit add into (lo, hi) with an overflow flag.
+__device__ void add_u128(unsigned long long* c, unsigned long long lo, unsigned long long hi,
+                         uint32_t* flag) {
+    if (lo) {
+        unsigned long long old = atomicAdd(c, lo);
+        if (old + lo < old) {
+            hi += 1;
+            if (hi == 0) atomicOr(flag, 1u);
+        }
+    }
+    if (hi) {
+        unsigned long long old = atomicAdd(c + 1, hi);
+        if (old + hi < old) atomicOr(flag, 1u);
+    }
+}
+
+// Per-wave LDS carve-out.
+struct Lds {
+    uint32_t* bound;     // [kMaxK][64]
+    uint32_t* anc;       // [kMaxK][64]
+    uint32_t* base_off;  // [64]
+    uint32_t* base_len;  // [64]
+    uint32_t* base_kind; // [64]: 0 out list, 1 in list, 2 level buffer
+    uint32_t* incl;      // [64]
+    uint32_t* segcnt;    // [64]
+    uint32_t* chk_off;   // [maxc][64]
+    uint32_t* chk_len;   // [maxc][64]
+    uint32_t* hist;      // [64][16]
+    uint32_t* st;        // wave state: cur[8], pofs[8], n[8]
+};
+
+__device__ __forceinline__ Lds carve(uint32_t* w, uint32_t maxc) {
+    Lds s;
+    s.bound = w;
+    s.anc = w + kMaxK * 64;
+    uint32_t* q = w + 2 * kMaxK * 64;
+    s.base_off = q;
+    s.base_len = q + 64;
+    s.base_kind = q + 128;
+    s.incl = q + 192;
+    s.segcnt = q + 256;
+    q += 6 * 64;
+    s.chk_off = q;
+    s.chk_len = q + maxc * 64;
+    q += 2 * maxc * 64;
+    s.st = q;
+    s.hist = q + 32;
+    return s;
+}
+
+struct Lvl {
+    uint32_t* node;
+    uint32_t* parent;  // level 0: first-level range start
+    uint32_t* segb;
+    uint32_t* segc;    // child count | kComplete
+    uint32_t* aux;     // level 0: first-level range end
+};
+
+__device__ __forceinline__ Lvl lvl_arrays(uint32_t* scr, uint32_t cap, uint32_t l) {
+    uint32_t* b = scr + (size_t)l * kLvlArrays * cap;
+    return {b, b + cap, b + 2 * cap, b + 3 * cap, b + 4 * cap};
+}
+
+struct Ctx {
+    const KArgs* a;
+    const PlanDesc* P;
+    uint32_t pi;
+    Lds s;
+    uint32_t* scr;
+    uint32_t lane;
+    unsigned long long acc_lo, acc_hi;  // per-lane 128-bit partial (leaf groups)
+    unsigned long long st_elems, st_fetch, st_pm;
+};
+
+// First-level base list length of root r for plan P (shortest constraint list).
+__device__ __forceinline__ uint32_t level1_len(const DevGraph& g, const PlanDesc* P, uint32_t r) {
+    const LevelDesc& D = P->lvl[1];
+    uint32_t best = kSkip;
+    for (uint32_t c = 0; c < D.n_cons; c++) {
+        const uint32_t* off = off_of(g, D.cons_dir[c]);
+        uint32_t l = off[r + 1] - off[r];
+        best = l < best ? l : best;
+    }
+    return best;
+}
+
+// Phase A of a level: lane = one partial match (parent) of the window.  Walks
+// the parent chain into LDS (bound nodes, ancestor indices) and picks the base
+// list and the lists to probe.  Returns the base length.
+template <bool IS_SIG>
+__device__ uint32_t phase_a(Ctx& C, const LevelDesc& D, uint32_t lv, uint32_t p, bool pv,
+                            bool walk) {
+    const KArgs& a = *C.a;
+    const DevGraph& g = a.g;
+    const uint32_t lane = C.lane;
+    uint32_t len = 0;
+    if (!pv) {
+        C.s.base_len[lane] = 0;
+        return 0;
+    }
+    if (walk) {
+        uint32_t idx = p;
+        for (int l = (int)lv - 1; l >= 0; --l) {
+            Lvl F = lvl_arrays(C.scr, a.cap, (uint32_t)l);
+            C.s.bound[l * 64 + lane] = F.node[idx];
+            C.s.anc[l * 64 + lane] = idx;
+            if (l > 0) idx = F.parent[idx];
+        }
+    }
+    bool fetched = false;
+    if (D.reuse != kNoReuse) {
+        uint32_t r = D.reuse;
+        uint32_t ai = C.s.anc[(r - 1) * 64 + lane];
+        Lvl F = lvl_arrays(C.scr, a.cap, r - 1);
+        uint32_t sc = F.segc[ai];
+        if (sc & kComplete) {
+            C.s.base_kind[lane] = 2;
+            C.s.base_off[lane] = F.segb[ai];
+            len = sc & ~kComplete;
+            for (uint32_t c = 0; c < D.n_cons; c++) {
+                uint32_t l = kSkip, o = 0;
+                if ((D.extra >> c) & 1u) {
+                    uint32_t nd = C.s.bound[D.cons_lvl[c] * 64 + lane];
+                    const uint32_t* off = off_of(g, D.cons_dir[c]);
+                    o = off[nd];
+                    l = off[nd + 1] - o;
+                }
+                C.s.chk_off[c * 64 + lane] = o;
+                C.s.chk_len[c * 64 + lane] = l;
+            }
+            fetched = true;
+        }
+    }
+    if (!fetched) {
+        uint32_t best = kSkip, bc = 0, bo = 0;
+        for (uint32_t c = 0; c < D.n_cons; c++) {
+            uint32_t nd = C.s.bound[D.cons_lvl[c] * 64 + lane];
+            const uint32_t* off = off_of(g, D.cons_dir[c]);
+            uint32_t o = off[nd];
+            uint32_t l = off[nd + 1] - o;
+            C.s.chk_off[c * 64 + lane] = o;
+            C.s.chk_len[c * 64 + lane] = l;
+            if (l < best) {
+                best = l;
+                bc = c;
+                bo = o;
+            }
+        }
+        C.s.chk_len[bc * 64 + lane] = kSkip;
+        C.s.base_kind[lane] = D.cons_dir[bc];
+        C.s.base_off[lane] = bo;
+        len = best;
+        if (!IS_SIG && lv == 1) {
+            // a root carries its first-level range [lo, hi)
+            Lvl F0 = lvl_arrays(C.scr, a.cap, 0);
+            uint32_t lo = F0.parent[p], hi = F0.aux[p];
+            hi = hi < len ? hi : len;
+            lo = lo < hi ? lo : hi;
+            C.s.base_off[lane] = bo + lo;
+            len = hi - lo;
+        }
+    }
+    C.s.base_len[lane] = len;
+    return len;
+}
+
+// Fetch base element `local` of window parent j.
+__device__ __forceinline__ uint32_t base_elem(const Ctx& C, uint32_t j, uint32_t local, uint32_t reuse) {
+    uint32_t kind = C.s.base_kind[j];
+    uint32_t off = C.s.base_off[j] + local;
+    if (kind == 2) return lvl_arrays(C.scr, C.a->cap, reuse).node[off];
+    return adj_of(C.a->g, kind)[off];
+}
+
+// Window parent of flattened element g: smallest j with incl[j] > g.
+__device__ __forceinline__ uint32_t find_parent(const Lds& s, uint32_t np, uint32_t g) {
+    uint32_t lo = 0, n = np;
+    while (n > 0) {
+        uint32_t h = n >> 1;
+        if (s.incl[lo + h] <= g) {
+            lo += h + 1;
+            n -= h + 1;
+        } else {
+            n = h;
+        }
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool check_elem(const Ctx& C, const LevelDesc& D, uint32_t lv, uint32_t j,
+                                           uint32_t x) {
+    const DevGraph& g = C.a->g;
+    bool ok = true;
+    uint32_t inj = D.inj;
+    for (uint32_t l = 0; l < lv; l++)
+        if ((inj >> l) & 1u) ok = ok && (x != C.s.bound[l * 64 + j]);
+    if (ok && D.deg_check) {
+        uint2 d = g.deg[x];
+        ok = d.x >= D.dmin_out && d.y >= D.dmin_in;
+    }
+    for (uint32_t c = 0; c < D.n_cons && ok; c++) {
+        uint32_t l = C.s.chk_len[c * 64 + j];
+        if (l != kSkip) ok = contains(adj_of(g, D.cons_dir[c]) + C.s.chk_off[c * 64 + j], l, x);
+    }
+    return ok;
+}
+
+// Membership of x in leaf signature s for window parent j (constraints only;
+// injectivity is common to all leaves and checked by the caller).
+__device__ __forceinline__ bool member_sig(const Ctx& C, const LevelDesc& S, uint32_t j, uint32_t x) {
+    const DevGraph& g = C.a->g;
+    bool ok = true;
+    for (uint32_t c = 0; c < S.n_cons && ok; c++) {
+        uint32_t nd = C.s.bound[S.cons_lvl[c] * 64 + j];
+        const uint32_t* off = off_of(g, S.cons_dir[c]);
+        uint32_t o = off[nd];
+        ok = contains(adj_of(g, S.cons_dir[c]) + o, off[nd + 1] - o, x);
+    }
+    return ok;
+}
+
+// Expand one window of level lv from the parents in level lv-1.  Returns the
+// number of children written to level lv's buffer.
+template <bool STATS>
+__device__ uint32_t expand(Ctx& C, uint32_t lv) {
+    const KArgs& a = *C.a;
+    const LevelDesc& D = C.P->lvl[lv];
+    const uint32_t lane = C.lane;
+    uint32_t* st = C.s.st;
+    const uint32_t nparents = uni(st[16 + lv - 1]);
+    const uint32_t cur = uni(st[lv]);
+    const uint32_t pofs = uni(st[8 + lv]);
+    const uint32_t p = cur + lane;
+    const bool pv = p < nparents;
+    uint32_t len = phase_a<false>(C, D, lv, p, pv, true);
+    if (pv && lane == 0) len -= pofs;
+    if (STATS && pv) {
+        C.st_elems += len;
+        C.st_fetch += 1;
+        for (uint32_t c = 0; c < D.n_cons; c++) {
+            uint32_t l = C.s.chk_len[c * 64 + lane];
+            if (l != kSkip) {
+                C.st_elems += l;
+                C.st_fetch += 1;
+            }
+        }
+    }
+    uint32_t incl = scan_incl(len, lane);
+    C.s.incl[lane] = incl;
+    const bool seg = (C.P->seg_src >> lv) & 1u;
+    if (seg) C.s.segcnt[lane] = 0;
+    const uint32_t cap = a.cap;
+    uint32_t np = uni((uint32_t)__popcll(__ballot(pv && incl <= cap)));
+    uint32_t T;
+    bool partial = false;
+    if (np == 0) {
+        // the first parent alone exceeds the buffer: take a slice of it
+        T = cap;
+        partial = true;
+        np = 1;
+        C.s.incl[0] = cap;
+    } else {
+        T = uni(__shfl(incl, (int)np - 1, 64));
+    }
+    wave_sync();
+    Lvl Fo = lvl_arrays(C.scr, cap, lv);
+    uint32_t nout = 0;
+    const uint32_t reuse = D.reuse;
+    for (uint32_t t0 = 0; t0 < T; t0 += 64) {
+        uint32_t gi = t0 + lane;
+        bool ok = gi < T;
+        uint32_t j = 0, x = 0;
+        if (ok) {
+            j = find_parent(C.s, np, gi);
+            uint32_t local = gi - (j ? C.s.incl[j - 1] : 0) + (j == 0 ? pofs : 0);
+            x = base_elem(C, j, local, reuse);
+            ok = check_elem(C, D, lv, j, x);
+        }
+        uint64_t m = __ballot(ok);
+        if (ok) {
+            uint32_t pos = nout + rank_below(m);
+            Fo.node[pos] = x;
+            Fo.parent[pos] = cur + j;
+            if (seg) atomicAdd(&C.s.segcnt[j], 1u);
+        }
+        nout += (uint32_t)__popcll(m);
+    }
+    if (STATS && lane == 0) C.st_pm += nout;
+    wave_sync();
+    if (seg) {
+        // children of each parent are contiguous in output order
+        uint32_t cnt = (lane < np) ? C.s.segcnt[lane] : 0;
+        uint32_t ex = scan_incl(cnt, lane) - cnt;
+        if (lane < np) {
+            Lvl Fi = lvl_arrays(C.scr, cap, lv - 1);
+            bool complete = !(lane == 0 && (pofs > 0 || partial));
+            if (lv == 1) {
+                // a root split into first-level sub-ranges never has all its children here
+                Lvl F0 = lvl_arrays(C.scr, cap, 0);
+                complete = complete && F0.parent[cur + lane] == 0 && F0.aux[cur + lane] == kSkip;
+            }
+            Fi.segb[cur + lane] = ex;
+            Fi.segc[cur + lane] = cnt | (complete ? kComplete : 0u);
+        }
+    }
+    // advance the cursor of this level
+    if (lane == 0) {
+        if (partial) {
+            st[8 + lv] = pofs + cap;
+        } else {
+            st[lv] = cur + np;
+            st[8 + lv] = 0;
+        }
+        st[16 + lv] = nout;
+    }
+    wave_sync();
+    return nout;
+}
+
+// Count the leaf group for every partial match in level `lv` (= e - 1).
+template <bool STATS>
+__device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
+    const KArgs& a = *C.a;
+    const PlanDesc* P = C.P;
+    const uint32_t lane = C.lane;
+    const uint32_t nsig = P->n_sig;
+    const bool linear = P->linear != 0;
+    const uint32_t nb = lv + 1;  // bound levels 0..lv
+    for (uint32_t w0 = 0; w0 < nprefix; w0 += 64) {
+        const uint32_t p = w0 + lane;
+        const bool pv = p < nprefix;
+        // walk the chain once: bound nodes of levels 0..lv
+        if (pv) {
+            uint32_t idx = p;
+            for (int l = (int)lv; l >= 0; --l) {
+                Lvl F = lvl_arrays(C.scr, a.cap, (uint32_t)l);
+                C.s.bound[l * 64 + lane] = F.node[idx];
+                C.s.anc[l * 64 + lane] = idx;
+                if (l > 0) idx = F.parent[idx];
+            }
+        }
+        if (!linear) {
+            for (int q = 0; q < 16; q++) C.s.hist[lane * 16 + q] = 0;
+        }
+        unsigned long long lin = 0;
+        for (uint32_t s = 0; s < nsig; s++) {
+            if (!P->sig_scan[s]) continue;
+            const LevelDesc& S = P->sig[s];
+            uint32_t len = phase_a<true>(C, S, nb, p, pv, false);
+            if (STATS && pv) {
+                C.st_elems += len;
+                C.st_fetch += 1;
+                for (uint32_t c = 0; c < S.n_cons; c++) {
+                    uint32_t l = C.s.chk_len[c * 64 + lane];
+                    if (l != kSkip) {
+                        C.st_elems += l;
+                        C.st_fetch += 1;
+                    }
+                }
+            }
+            uint32_t incl = scan_incl(len, lane);
+            C.s.incl[lane] = incl;
+            const uint32_t T = uni(__shfl(incl, 63, 64));
+            const uint32_t np = 64;
+            wave_sync();
+            const uint8_t implied = P->sig_implied[s];
+            const uint8_t test = P->sig_test[s];
+            const uint32_t below = (1u << s) - 1u;
+            for (uint32_t t0 = 0; t0 < T; t0 += 64) {
+                uint32_t gi = t0 + lane;
+                bool ok = gi < T;
+                uint32_t j = 0, x = 0;
+                if (ok) {
+                    j = find_parent(C.s, np, gi);
+                    uint32_t local = gi - (j ? C.s.incl[j - 1] : 0);
+                    x = base_elem(C, j, local, S.reuse);
+                    ok = check_elem(C, S, nb, j, x);
+                }
+                if (linear) {
+                    lin += (unsigned long long)__popcll(__ballot(ok));
+                } else if (ok) {
+                    uint32_t mask = implied;
+                    for (uint32_t s2 = 0; s2 < nsig; s2++)
+                        if (((test >> s2) & 1u) && member_sig(C, P->sig[s2], j, x)) mask |= 1u << s2;
+                    if ((mask & below) == 0) atomicAdd(&C.s.hist[j * 16 + mask], 1u);
+                }
+            }
+            wave_sync();
+        }
+        if (linear) {
+            if (lane == 0) {
+                unsigned long long o = C.acc_lo;
+                C.acc_lo += lin;
+                if (C.acc_lo < o) C.acc_hi += 1;
+            }
+        } else if (pv) {
+            // inclusion-exclusion over set partitions of the leaves
+            uint32_t full = (1u << nsig) - 1u;
+            uint64_t I[16];
+            for (uint32_t m = 1; m <= full; m++) {
+                uint64_t sum = 0;
+                for (uint32_t m2 = m; m2 <= full; m2++)
+                    if ((m2 & m) == m) sum += C.s.hist[lane * 16 + m2];
+                I[m] = sum;
+            }
+            __int128 val = 0;
+            for (uint32_t t = 0; t < P->n_terms; t++) {
+                const Term& tm = P->terms[t];
+                __int128 prod = tm.coef;
+                for (uint32_t b = 0; b < tm.nb; b++) prod *= (__int128)I[tm.mask[b]];
+                val += prod;
+            }
+            unsigned __int128 v = (unsigned __int128)val;
+            unsigned long long vl = (unsigned long long)v, vh = (unsigned long long)(v >> 64);
+            unsigned long long o = C.acc_lo;
+            C.acc_lo += vl;
+            C.acc_hi += vh + (C.acc_lo < o ? 1ull : 0ull);
+        }
+        wave_sync();
+    }
+}
+
+template <bool STATS>
+__device__ void flush(Ctx& C) {
+    unsigned long long lo = C.acc_lo, hi = C.acc_hi;
+    // wave reduction of 128-bit partials
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        unsigned long long olo = __shfl_xor(lo, d, 64);
+        unsigned long long ohi = __shfl_xor(hi, d, 64);
+        unsigned long long nlo = lo + olo;
+        hi = hi + ohi + (nlo < lo ? 1ull : 0ull);
+        lo = nlo;
+    }
+    if (C.lane == 0 && (lo | hi))
+        add_u128(C.a->counts + 2 * C.pi, lo, hi, C.a->plan_flags + C.pi);
+    C.acc_lo = C.acc_hi = 0;
+    if (STATS) {
+        unsigned long long e = C.st_elems, f = C.st_fetch, m = C.st_pm;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+            e += __shfl_xor(e, d, 64);
+            f += __shfl_xor(f, d, 64);
+            m += __shfl_xor(m, d, 64);
+        }
+        if (C.lane == 0) {
+            unsigned long long* sp = C.a->stats + 4 * C.pi;
+            if (e) atomicAdd(sp + 0, e);
+            if (f) atomicAdd(sp + 1, f);
+            if (m) atomicAdd(sp + 2, m);
+        }
+        C.st_elems = C.st_fetch = C.st_pm = 0;
+    }
+}
+
+// Depth-first exploration of the roots held in level 0.
+template <bool STATS>
+__device__ void explore(Ctx& C, uint32_t n0) {
+    const uint32_t e = C.P->e;
+    uint32_t* st = C.s.st;
+    if (e == 1) {
+        count_leaves<STATS>(C, 0, n0);
+        return;
+    }
+    if (C.lane == 0) {
+        st[16 + 0] = n0;
+        st[1] = 0;
+        st[8 + 1] = 0;
+    }
+    wave_sync();
+    uint32_t lv = 1;
+    for (;;) {
+        uint32_t nparents = uni(st[16 + lv - 1]);
+        uint32_t cur = uni(st[lv]);
+        if (cur >= nparents) {
+            if (lv == 1) break;
+            lv -= 1;
+            continue;
+        }
+        uint32_t nout = expand<STATS>(C, lv);
+        if (lv == e - 1) {
+            if (nout) count_leaves<STATS>(C, lv, nout);
+        } else if (nout) {
+            lv += 1;
+            if (C.lane == 0) {
+                st[lv] = 0;
+                st[8 + lv] = 0;
+            }
+            wave_sync();
+        }
+    }
+}
+
+template <bool STATS>
+__global__ void __launch_bounds__(kBlockThreads) count_kernel(KArgs a) {
+    extern __shared__ uint32_t smem[];
+    Ctx C;
+    C.a = &a;
+    C.lane = lane_id();
+    const uint32_t wid = threadIdx.x >> 6;
+    C.s = carve(smem + wid * a.lds_words, a.maxc);
+    const uint64_t gw = (uint64_t)blockIdx.x * kWavesPerBlock + wid;
+    C.scr = a.scratch + gw * (uint64_t)a.wave_words;
+    C.acc_lo = C.acc_hi = 0;
+    C.st_elems = C.st_fetch = C.st_pm = 0;
+    const uint32_t split_count = uni(__atomic_load_n(&a.ctl[kCtlSplitCount], __ATOMIC_RELAXED));
+    const uint32_t n_split = split_count < a.split_cap ? split_count : a.split_cap;
+    const uint32_t chunks_per_plan = (a.n_src + a.chunk - 1) / a.chunk;
+    const uint32_t total_chunks = chunks_per_plan * a.n_plans;
+    Lvl F0 = lvl_arrays(C.scr, a.cap, 0);
+    for (;;) {
+        // ---- take a task
+        uint32_t kind = 2, item = 0;
+        if (C.lane == 0) {
+            bool stop = false;
+            if (a.cancel && __atomic_load_n(a.cancel, __ATOMIC_RELAXED) != 0) {
+                atomicOr(&a.ctl[kCtlCancelled], 1u);
+                stop = true;
+            }
+            if (!stop && __atomic_load_n(&a.ctl[kCtlSplitHead], __ATOMIC_RELAXED) < n_split) {
+                uint32_t it = atomicAdd(&a.ctl[kCtlSplitHead], 1u);
+                if (it < n_split) {
+                    kind = 0;
+                    item = it;
+                }
+            }
+            if (!stop && kind == 2) {
+                uint32_t c = atomicAdd(&a.ctl[kCtlRootCursor], 1u);
+                if (c < total_chunks) {
+                    kind = 1;
+                    item = c;
+                }
+            }
+        }
+        kind = uni(__shfl(kind, 0, 64));
+        item = uni(__shfl(item, 0, 64));
+        if (kind == 2) break;
+        uint32_t n0 = 0;
+        if (kind == 0) {
+            uint4 it = a.split_items[item];
+            C.pi = uni(it.x);
+            C.P = a.plans + C.pi;
+            if (C.lane == 0) {
+                F0.node[0] = it.y;
+                F0.parent[0] = it.z;
+                F0.aux[0] = it.w;
+            }
+            n0 = 1;
+        } else {
+            // interleave plans so that all of them start on the low (hub) ids
+            C.pi = uni(item % a.n_plans);
+            C.P = a.plans + C.pi;
+            const uint32_t ci = item / a.n_plans;
+            const uint32_t first = ci * a.chunk;
+            const uint32_t idx = first + C.lane;
+            bool ok = C.lane < a.chunk && idx < a.n_src;
+            uint32_t r = 0;
+            if (ok) {
+                r = a.roots ? a.roots[idx] : idx;
+                ok = r < a.g.n;
+            }
+            if (ok) {
+                uint2 d = a.g.deg[r];
+                ok = d.x >= C.P->root_dout && d.y >= C.P->root_din;
+            }
+            if (ok && C.P->e >= 2) {
+                uint32_t l = level1_len(a.g, C.P, r);
+                ok = l > 0 && l <= a.split;  // longer lists were queued by the split kernel
+            }
+            uint64_t m = __ballot(ok);
+            if (ok) {
+                uint32_t pos = rank_below(m);
+                F0.node[pos] = r;
+                F0.parent[pos] = 0;
+                F0.aux[pos] = kSkip;
+            }
+            n0 = (uint32_t)__popcll(m);
+        }
+        wave_sync();
+        if (STATS && C.lane == 0) atomicAdd(a.stats + 4 * C.pi + 3, (unsigned long long)n0);
+        if (n0) explore<STATS>(C, n0);
+        flush<STATS>(C);
+    }
+}
+
+// Hub roots whose first-level list is longer than `split` become several
+// queued sub-range tasks.  Must agree with the root filter of count_kernel.
+__global__ void split_kernel(KArgs a) {
+    const uint32_t nsrc = a.roots ? a.n_src : a.n_hubs;
+    const uint64_t total = (uint64_t)nsrc * a.n_plans;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t pi = (uint32_t)(i / nsrc);
+        uint32_t h = (uint32_t)(i % nsrc);
+        const PlanDesc* P = a.plans + pi;
+        if (P->e < 2) continue;
+        uint32_t r = a.roots ? a.roots[h] : a.hubs[h];
+        if (r >= a.g.n) continue;
+        uint2 d = a.g.deg[r];
+        if (d.x < P->root_dout || d.y < P->root_din) continue;
+        uint32_t len = level1_len(a.g, P, r);
+        if (len <= a.split) continue;
+        uint32_t nit = (len + a.split - 1) / a.split;
+        uint32_t base = atomicAdd(&a.ctl[kCtlSplitCount], nit);
+        if (base + nit > a.split_cap) {
+            atomicOr(&a.ctl[kCtlQueueFull], 1u);
+            continue;
+        }
+        for (uint32_t q = 0; q < nit; q++) {
+            uint32_t lo = q * a.split;
+            uint32_t hi = lo + a.split < len ? lo + a.split : len;
+            a.split_items[base + q] = make_uint4(pi, r, lo, hi);
+        }
+    }
+}
+
+// Copy plan descriptors into the workspace table and clear control state.
+__global__ void init_kernel(InitArgs a) {
+    const uint32_t words = sizeof(PlanDesc) / 4;
+    const uint32_t tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nthr = gridDim.x * blockDim.x;
+    for (uint32_t i = tid; i < a.count * words; i += nthr) {
+        uint32_t pl = i / words, w = i % words;
+        reinterpret_cast<uint32_t*>(a.table + a.first + pl)[w] =
+            reinterpret_cast<const uint32_t*>(a.src[pl])[w];
+    }
+    if (a.zero_ctl) {
+        for (uint32_t i = tid; i < kCtlWords; i += nthr) a.ctl[i] = 0;
+        for (uint32_t i = tid; i < a.n_plans; i += nthr) a.plan_flags[i] = 0;
+        for (uint32_t i = tid; i < 2 * a.n_plans; i += nthr) a.counts[i] = 0;
+        if (a.stats)
+            for (uint32_t i = tid; i < 4 * a.n_plans; i += nthr) a.stats[i] = 0;
+    }
+}
+
+// Per-plan status from the flags the count kernel raised.
+__global__ void finalize_kernel(KArgs a) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n_plans; i += gridDim.x * blockDim.x) {
+        int32_t st = 0;
+        if (a.ctl[kCtlQueueFull]) st = -6;
+        else if (a.ctl[kCtlCancelled]) st = -7;
+        else if (a.plan_flags[i] & 1u) st = -5;
+        a.status[i] = st;
+    }
+}
+
+hipError_t launch_count(const InitArgs* inits, int n_inits, const KArgs& a, uint32_t n_blocks,
+                        bool stats, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_stop) {
+    for (int i = 0; i < n_inits; i++) {
+        hipLaunchKernelGGL(init_kernel, dim3(64), dim3(256), 0, stream, inits[i]);
+    }
+    uint32_t nsrc = a.roots ? a.n_src : a.n_hubs;
+    uint64_t total = (uint64_t)nsrc * a.n_plans;
+    uint32_t sb = (uint32_t)((total + 255) / 256);
+    sb = sb < 1 ? 1 : (sb > 4096 ? 4096 : sb);
+    hipLaunchKernelGGL(split_kernel, dim3(sb), dim3(256), 0, stream, a);
+    size_t lds = (size_t)a.lds_words * 4 * kWavesPerBlock;
+    if (ev_start) {
+        hipError_t e = hipEventRecord(ev_start, stream);
+        if (e != hipSuccess) return e;
+    }
+    if (stats)
+        hipLaunchKernelGGL(count_kernel<true>, dim3(n_blocks), dim3(kBlockThreads), lds, stream, a);
+    else
+        hipLaunchKernelGGL(count_kernel<false>, dim3(n_blocks), dim3(kBlockThreads), lds, stream, a);
+    if (ev_stop) {
+        hipError_t e = hipEventRecord(ev_stop, stream);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace xm

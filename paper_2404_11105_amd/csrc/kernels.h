@@ -1,0 +1,85 @@
+// kernels.h — launch interface between the host runtime and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "plan_ir.h"
+
+namespace xm {
+
+constexpr int kWavesPerBlock = 4;
+constexpr int kBlockThreads = 64 * kWavesPerBlock;
+constexpr uint32_t kHubMin = 64;    // nodes with a list longer than this are hub candidates
+constexpr int kMaxPlansPerInit = 240;
+constexpr int kLvlArrays = 5;       // node, parent, seg_begin, seg_count, aux per level
+
+// Control words at the start of the workspace.
+enum Ctl : uint32_t {
+    kCtlRootCursor = 0,   // next root chunk
+    kCtlSplitHead = 1,    // next split item
+    kCtlSplitCount = 2,   // split items written by the split kernel
+    kCtlCancelled = 3,    // a wave saw the cancel flag
+    kCtlQueueFull = 4,    // split queue overflow (cannot happen with a sized workspace)
+    kCtlWords = 64
+};
+
+struct DevGraph {
+    const uint32_t* out_off;
+    const uint32_t* out_adj;
+    const uint32_t* in_off;
+    const uint32_t* in_adj;
+    const uint2* deg;   // (out-degree, in-degree)
+    uint32_t n;
+    uint32_t pad;
+};
+
+struct KArgs {
+    DevGraph g;
+    const PlanDesc* plans;      // table in the workspace
+    uint32_t n_plans;
+    uint32_t chunk;             // roots per root work item (<= 64)
+    uint32_t split;             // first-level lists longer than this are split
+    uint32_t cap;               // entries per level buffer
+    uint32_t* ctl;              // control words
+    uint32_t* plan_flags;       // per plan: bit 0 overflow
+    uint4* split_items;         // (plan, root, lo, hi)
+    uint32_t split_cap;
+    uint32_t n_src;             // roots: subset size or n
+    const uint32_t* roots;      // subset or NULL (then root i is node i)
+    const uint32_t* hubs;       // hub candidates for the split kernel (when roots == NULL)
+    uint32_t n_hubs;
+    uint32_t lds_words;         // LDS words per wave
+    uint32_t maxc;              // largest constraint count over plans and signatures
+    uint32_t wave_words;        // scratch words per wave
+    uint32_t* scratch;          // n_waves * wave_words
+    unsigned long long* counts; // 2 per plan
+    int32_t* status;            // 1 per plan
+    const int32_t* cancel;      // nullable
+    unsigned long long* stats;  // nullable: 4 per plan
+};
+
+struct InitArgs {
+    PlanDesc* table;
+    const PlanDesc* src[kMaxPlansPerInit];
+    uint32_t first, count;      // plans [first, first+count) of the table
+    uint32_t n_plans;
+    uint32_t zero_ctl;          // 1: also clear control words, flags, counts, stats
+    uint32_t* ctl;
+    uint32_t* plan_flags;
+    unsigned long long* counts;
+    unsigned long long* stats;
+};
+
+// LDS words per wave for a given largest constraint count and leaf mode.
+inline uint32_t lds_words_for(uint32_t maxc, bool nonlinear) {
+    return 2 * kMaxK * 64      // bound values, ancestor indices
+           + 6 * 64            // base offset/length/kind, inclusive scan, segment counts, spare
+           + 2 * maxc * 64     // check-list offset/length per constraint
+           + (nonlinear ? 16 * 64 : 0)  // leaf-group histograms
+           + 32;               // wave state
+}
+
+hipError_t launch_count(const InitArgs* inits, int n_inits, const KArgs& a, uint32_t n_blocks,
+                        bool stats, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_stop);
+
+}  // namespace xm

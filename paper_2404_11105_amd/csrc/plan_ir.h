@@ -1,0 +1,79 @@
+// plan_ir.h — the compact plan descriptor read by the count kernel.
+//
+// A plan binds pattern vertices level by level (section 5.1: a
+// materialisation order of vertices and an exploration order of edges).
+// Level 0 is the start vertex (its images are the roots, Algorithm 2's
+// "init A^{p.start}").  Levels 1..e-1 are enumerated: each partial match is
+// extended by every candidate of the next level (Algorithm 2, Explore).  The
+// trailing vertices are a leaf group: they have no arcs among themselves, so
+// once levels 0..e-1 are bound their candidate sets are fixed and the number
+// of injective completions is computed from set sizes instead of being
+// enumerated (section 5.3, counting by multiplying candidate-set sizes, made
+// exact for overlapping sets by inclusion-exclusion over set partitions).
+//
+// Candidates of a level satisfy:
+//   * one membership per constraint (j, dir): x in out(phi(v_j)) for dir 0,
+//     x in in(phi(v_j)) for dir 1 (Definition 2.2 edge constraints, with the
+//     direction check of Algorithm 2's out_arcs / in_arcs choice);
+//   * x != phi(v_j) for the levels j in `inj` (the visited marks of
+//     Algorithm 2);
+//   * out-degree >= dmin_out and in-degree >= dmin_in (the degree vertex
+//     constraint, section 2, split into its two directions).
+// A level with reuse = r takes its base from the candidates already found for
+// level r under the same ancestors (section 5.2 intermediate-result reuse: an
+// included constraint is materialised from the including one's result) and
+// checks only the constraints in `extra`.
+#pragma once
+#include <stdint.h>
+
+namespace xm {
+
+constexpr int kMaxK = 7;          // pattern vertices
+constexpr int kMaxCons = 12;      // constraints of one level (bidirected: 2 per earlier level)
+constexpr int kMaxSig = 4;        // distinct leaf signatures
+constexpr int kMaxLeaves = 6;     // vertices in the leaf group
+constexpr int kMaxTerms = 96;     // inclusion-exclusion terms after merging
+constexpr int kMaxBlocks = 6;     // blocks in one term
+constexpr uint8_t kNoReuse = 0xFF;
+
+struct LevelDesc {
+    uint8_t n_cons;
+    uint8_t reuse;                // kNoReuse or an enumerated level r >= 1
+    uint8_t inj;                  // bit j: check x != phi(v_j)
+    uint8_t deg_check;            // 1: check degree thresholds
+    uint16_t extra;               // when reusing: bit c -> check constraint c
+    uint16_t pad0;
+    uint8_t cons_lvl[kMaxCons];
+    uint8_t cons_dir[kMaxCons];   // 0: out(phi(v_j)), 1: in(phi(v_j))
+    uint32_t dmin_out, dmin_in;
+};
+
+struct Term {
+    int32_t coef;                 // Moebius coefficient, merged
+    uint8_t nb;                   // blocks
+    uint8_t mask[kMaxBlocks];     // signature mask of each block (intersection of those sets)
+    uint8_t pad;
+};
+
+struct PlanDesc {
+    uint32_t k;                   // pattern vertices
+    uint32_t e;                   // enumerated levels including the start vertex (1..k-1)
+    uint32_t root_dout, root_din; // degree thresholds of the start vertex
+    uint32_t seg_src;             // bit r: level r is a reuse source (track children)
+    uint32_t n_sig;               // distinct leaf signatures (1..kMaxSig)
+    uint32_t t;                   // leaves
+    uint32_t linear;              // 1: one leaf -> the count is a plain sum of set sizes
+    uint32_t n_terms;
+    uint32_t pad1;
+    LevelDesc lvl[kMaxK];         // [1..e-1]
+    LevelDesc sig[kMaxSig];       // leaf signatures (inj over levels < e)
+    uint8_t sig_mult[kMaxSig];    // leaves per signature
+    uint8_t sig_scan[kMaxSig];    // 1: enumerate this signature's base for the union
+    uint8_t sig_implied[kMaxSig]; // membership in sig s implies membership in these (incl. s)
+    uint8_t sig_test[kMaxSig];    // memberships to test for elements of sig s
+    uint8_t order[kMaxK];         // level -> pattern vertex (reporting)
+    uint8_t pad2[4];
+    Term terms[kMaxTerms];
+};
+
+}  // namespace xm

@@ -1,0 +1,653 @@
+// planner.cpp — host-side pattern reduction and plan generation.
+//
+// Section 4.1 (finding constraint inclusion): edges that share a source, or
+// share a destination, are related by inclusion (Theorem 2.1); for each
+// vertex the in-edge from its smallest-degree in-neighbour includes the other
+// in-edges, and likewise for out-edges.  Section 4.2 (reducing the pattern):
+// the edges kept form a constraint cover (Definition "Constraint Cover"); its
+// weighted minimum is the objective argmin sum ||A_e||; Algorithm 1 is the
+// paper's greedy for it.  Section 5.1 (plan generation): start at the
+// reduction's start vertex, materialise it, then extend to the vertex
+// adjacent to the visited ones that is most constrained.
+//
+// The plan emitted here (plan_ir.h) is what the count kernel executes:
+//   reduced   - siblings with included constraint sets reuse the candidate
+//               set already materialised for the including level (section
+//               5.2), and the trailing independent vertices are counted by
+//               product (section 5.3) with an exact inclusion-exclusion
+//               correction for injectivity;
+//   unreduced - every level materialises all of its constraints from the data
+//               graph; only the last vertex is counted instead of enumerated.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "planner.h"
+
+namespace xm {
+
+namespace {
+
+inline int popc(uint32_t x) { return __builtin_popcount(x); }
+
+struct Pat {
+    int k = 0;
+    uint32_t out[kMaxK] = {0};  // bit w: arc v -> w
+    uint32_t in[kMaxK] = {0};   // bit u: arc u -> v
+    std::vector<std::pair<int, int>> arcs;  // distinct, sorted
+    int dout(int v) const { return popc(out[v]); }
+    int din(int v) const { return popc(in[v]); }
+    int deg(int v) const { return dout(v) + din(v); }
+    uint32_t nbr(int v) const { return out[v] | in[v]; }
+};
+
+bool connected(const Pat& p, uint32_t vmask) {
+    if (!vmask) return true;
+    int s = __builtin_ctz(vmask);
+    uint32_t seen = 1u << s, frontier = seen;
+    while (frontier) {
+        uint32_t nxt = 0;
+        for (int v = 0; v < p.k; v++)
+            if (frontier & (1u << v)) nxt |= p.nbr(v) & vmask;
+        nxt &= ~seen;
+        seen |= nxt;
+        frontier = nxt;
+    }
+    return seen == vmask;
+}
+
+// ---------------------------------------------------------------------------
+// Inclusion analysis and constraint covers (reported in the plan JSON).
+// ---------------------------------------------------------------------------
+struct CoverReport {
+    std::vector<int> groups_in_rep, groups_out_rep;  // representative arc index per vertex, -1 if none
+    std::vector<int> min_cover;                       // arc indices
+    double min_cover_weight = 0;
+    std::vector<int> greedy_cover;                    // Algorithm 1's split queue
+    int greedy_start = -1;
+};
+
+// Arc e = (u, w) includes every arc leaving u and every arc entering w
+// (Theorem 2.1 applied to shared sources and shared destinations).
+uint64_t inclusion_set(const Pat& p, int e) {
+    uint64_t s = 0;
+    int u = p.arcs[e].first, w = p.arcs[e].second;
+    for (size_t f = 0; f < p.arcs.size(); f++)
+        if (p.arcs[f].first == u || p.arcs[f].second == w) s |= 1ull << f;
+    return s;
+}
+
+void min_cover_bb(const std::vector<uint64_t>& inc, const std::vector<double>& w, uint64_t all,
+                  uint64_t covered, double cost, std::vector<int>& cur, double& best,
+                  std::vector<int>& best_set) {
+    if (cost >= best - 1e-12) return;
+    if (covered != all) {
+        // every further arc covers at most max_inc uncovered arcs and costs >= min_w
+        int left = __builtin_popcountll(all & ~covered), max_inc = 1;
+        double min_w = 1e300;
+        for (size_t e = 0; e < inc.size(); e++) {
+            max_inc = std::max(max_inc, __builtin_popcountll(inc[e] & ~covered));
+            min_w = std::min(min_w, w[e]);
+        }
+        if (cost + ((left + max_inc - 1) / max_inc) * min_w >= best - 1e-12) return;
+    }
+    if (covered == all) {
+        best = cost;
+        best_set = cur;
+        return;
+    }
+    int first = __builtin_ctzll(all & ~covered);
+    for (size_t e = 0; e < inc.size(); e++) {
+        if (!(inc[e] & (1ull << first))) continue;
+        cur.push_back((int)e);
+        min_cover_bb(inc, w, all, covered | inc[e], cost + w[e], cur, best, best_set);
+        cur.pop_back();
+    }
+}
+
+CoverReport analyse_cover(const Pat& p, const GraphStats* gs, int start) {
+    CoverReport r;
+    int na = (int)p.arcs.size();
+    r.groups_in_rep.assign(p.k, -1);
+    r.groups_out_rep.assign(p.k, -1);
+    // Section 4.1: the smallest-degree in-neighbour's edge represents the
+    // in-group (ties: lowest vertex id); same for out-neighbours.
+    for (int v = 0; v < p.k; v++) {
+        int best_in = -1, best_out = -1;
+        for (int e = 0; e < na; e++) {
+            int a = p.arcs[e].first, b = p.arcs[e].second;
+            if (b == v && (best_in < 0 || p.deg(a) < p.deg(p.arcs[best_in].first))) best_in = e;
+            if (a == v && (best_out < 0 || p.deg(b) < p.deg(p.arcs[best_out].second))) best_out = e;
+        }
+        r.groups_in_rep[v] = best_in;
+        r.groups_out_rep[v] = best_out;
+    }
+    // Weights ||A_e||: expected arcs of the data graph that satisfy the degree
+    // constraints of both endpoints (unit weights without a graph).
+    std::vector<double> w(na, 1.0);
+    if (gs && gs->m > 0) {
+        for (int e = 0; e < na; e++) {
+            int a = p.arcs[e].first, b = p.arcs[e].second;
+            int ta = std::min(p.dout(a), 7), tb = std::min(p.din(b), 7);
+            w[e] = std::max(1e-9, (double)gs->m * gs->frac_out_ge[ta] * gs->frac_in_ge[tb]);
+        }
+    }
+    std::vector<uint64_t> inc(na);
+    for (int e = 0; e < na; e++) inc[e] = inclusion_set(p, e);
+    uint64_t all = (na == 64) ? ~0ull : ((1ull << na) - 1);
+    double best = 1e300;
+    std::vector<int> cur;
+    min_cover_bb(inc, w, all, 0, 0.0, cur, best, r.min_cover);
+    std::sort(r.min_cover.begin(), r.min_cover.end());
+    r.min_cover_weight = best;
+
+    // Algorithm 1 (greedy), readings: the outer loop takes the lowest-index
+    // unvisited arc and restarts from its larger-degree endpoint;
+    // findMaxECoverage picks the unvisited arc at v that covers the most
+    // unvisited arcs (ties: smaller degree of its other endpoint, then lowest
+    // index); Neighbor_MaxDegree is the max-degree vertex that still has an
+    // unvisited arc and is adjacent to a vertex already reached.
+    uint64_t visited = 0;
+    uint32_t reached = 1u << start;
+    r.greedy_start = start;
+    auto search_split = [&](int u) {
+        int v = u;
+        while (v >= 0) {
+            reached |= 1u << v;
+            for (;;) {
+                int mec = -1, mec_cov = -1;
+                for (int e = 0; e < na; e++) {
+                    if (visited & (1ull << e)) continue;
+                    int a = p.arcs[e].first, b = p.arcs[e].second;
+                    if (a != v && b != v) continue;
+                    int cov = __builtin_popcountll(inc[e] & ~visited);
+                    int other = (a == v) ? b : a;
+                    int mo = mec >= 0 ? ((p.arcs[mec].first == v) ? p.arcs[mec].second : p.arcs[mec].first) : 0;
+                    if (cov > mec_cov || (cov == mec_cov && p.deg(other) < p.deg(mo))) {
+                        mec = e;
+                        mec_cov = cov;
+                    }
+                }
+                if (mec < 0) break;
+                r.greedy_cover.push_back(mec);
+                visited |= inc[mec];  // updateVInclusion: included arcs are removed
+                int a = p.arcs[mec].first, b = p.arcs[mec].second;
+                reached |= (1u << a) | (1u << b);
+            }
+            int nv = -1;
+            for (int x = 0; x < p.k; x++) {
+                bool has = false;
+                for (int e = 0; e < na; e++)
+                    if (!(visited & (1ull << e)) && (p.arcs[e].first == x || p.arcs[e].second == x)) has = true;
+                if (!has) continue;
+                bool adj = (reached & (1u << x)) || (p.nbr(x) & reached);
+                if (!adj) continue;
+                if (nv < 0 || p.deg(x) > p.deg(nv)) nv = x;
+            }
+            v = nv;
+        }
+    };
+    search_split(start);
+    while (visited != all) {
+        int e = __builtin_ctzll(all & ~visited);
+        int a = p.arcs[e].first, b = p.arcs[e].second;
+        search_split(p.deg(a) <= p.deg(b) ? b : a);
+    }
+    std::sort(r.greedy_cover.begin(), r.greedy_cover.end());
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Plan construction
+// ---------------------------------------------------------------------------
+struct LeafSig {
+    uint32_t in_mask, out_mask;  // pattern vertices u with u -> leaf / leaf -> u
+    bool operator<(const LeafSig& o) const {
+        int a = popc(in_mask) + popc(out_mask), b = popc(o.in_mask) + popc(o.out_mask);
+        if (a != b) return a < b;
+        if (in_mask != o.in_mask) return in_mask < o.in_mask;
+        return out_mask < o.out_mask;
+    }
+    bool operator==(const LeafSig& o) const { return in_mask == o.in_mask && out_mask == o.out_mask; }
+    bool subset_of(const LeafSig& o) const {
+        return (in_mask & ~o.in_mask) == 0 && (out_mask & ~o.out_mask) == 0;
+    }
+};
+
+// Set partitions of `t` leaves -> merged Moebius terms.
+// injective tuples = sum over partitions pi of prod_{B in pi} (-1)^{|B|-1} (|B|-1)!
+//                    * |intersection of the sets of the leaves in B|
+bool leaf_terms(const std::vector<int>& leaf_sig, std::vector<Term>& out) {
+    int t = (int)leaf_sig.size();
+    std::map<std::vector<uint8_t>, long long> acc;
+    std::vector<int> rgs(t, 0);
+    // restricted growth strings enumerate set partitions
+    for (;;) {
+        int nb = 0;
+        for (int i = 0; i < t; i++) nb = std::max(nb, rgs[i] + 1);
+        std::vector<uint8_t> masks(nb, 0);
+        std::vector<int> sz(nb, 0);
+        for (int i = 0; i < t; i++) {
+            masks[rgs[i]] |= (uint8_t)(1u << leaf_sig[i]);
+            sz[rgs[i]]++;
+        }
+        long long coef = 1;
+        for (int b = 0; b < nb; b++) {
+            long long f = 1;
+            for (int x = 2; x < sz[b]; x++) f *= x;
+            coef *= ((sz[b] - 1) % 2 ? -1 : 1) * f;
+        }
+        std::sort(masks.begin(), masks.end());
+        acc[masks] += coef;
+        // next restricted growth string
+        int i = t - 1;
+        while (i > 0) {
+            int mx = 0;
+            for (int j = 0; j < i; j++) mx = std::max(mx, rgs[j]);
+            if (rgs[i] <= mx) {
+                rgs[i]++;
+                for (int j = i + 1; j < t; j++) rgs[j] = 0;
+                break;
+            }
+            i--;
+        }
+        if (i == 0) break;
+    }
+    out.clear();
+    for (auto& kv : acc) {
+        if (kv.second == 0) continue;
+        Term tm;
+        std::memset(&tm, 0, sizeof(tm));
+        tm.coef = (int32_t)kv.second;
+        tm.nb = (uint8_t)kv.first.size();
+        for (size_t b = 0; b < kv.first.size(); b++) tm.mask[b] = kv.first[b];
+        out.push_back(tm);
+    }
+    return (int)out.size() <= kMaxTerms;
+}
+
+struct Cand {
+    std::vector<int> order;   // enumerated vertices (level order)
+    std::vector<int> leaves;  // leaf vertices
+    double cost = 0;
+};
+
+// Greedy order of the enumerated vertices (section 5.1): start vertex, then
+// repeatedly the unvisited vertex adjacent to the visited ones with the most
+// arcs to them (ties: larger degree, then lowest id).
+std::vector<int> enum_order(const Pat& p, int start, uint32_t emask) {
+    std::vector<int> ord{start};
+    uint32_t bound = 1u << start;
+    while ((int)ord.size() < popc(emask)) {
+        int best = -1, bc = -1;
+        for (int v = 0; v < p.k; v++) {
+            if (!(emask & (1u << v)) || (bound & (1u << v))) continue;
+            int c = popc(p.out[v] & bound) + popc(p.in[v] & bound);
+            if (c == 0) continue;
+            if (c > bc || (c == bc && p.deg(v) > p.deg(best))) {
+                best = v;
+                bc = c;
+            }
+        }
+        if (best < 0) break;
+        ord.push_back(best);
+        bound |= 1u << best;
+    }
+    return ord;
+}
+
+// Rough work model on a random graph with n nodes and average degree d:
+// a level with c constraints keeps d * (d/n)^(c-1) candidates per partial
+// match and costs about d element reads per partial match.
+double model_cost(const Pat& p, const std::vector<int>& ord, int n_scan, const GraphStats* gs) {
+    double n = (gs && gs->n) ? (double)gs->n : 1e6;
+    double d = (gs && gs->n) ? std::max(1.0, (double)gs->m / (double)gs->n) : 16.0;
+    double P = n, cost = n;
+    uint32_t bound = 1u << ord[0];
+    for (size_t i = 1; i < ord.size(); i++) {
+        int v = ord[i];
+        int c = popc(p.out[v] & bound) + popc(p.in[v] & bound);
+        cost += P * d;
+        P *= d * std::pow(d / n, c - 1);
+        bound |= 1u << v;
+    }
+    cost += P * d * n_scan;
+    return cost;
+}
+
+void fill_level(const Pat& p, const std::vector<int>& lvl_of, int v, int nlv_limit,
+                uint32_t later_mask, LevelDesc& L) {
+    std::memset(&L, 0, sizeof(L));
+    L.reuse = kNoReuse;
+    uint32_t cons_lv = 0;
+    for (int j = 0; j < nlv_limit; j++) {
+        int u = -1;
+        for (int x = 0; x < p.k; x++)
+            if (lvl_of[x] == j) u = x;
+        if (u < 0) continue;
+        if (p.out[u] & (1u << v)) {  // u -> v: v in out(phi(u))
+            L.cons_lvl[L.n_cons] = (uint8_t)j;
+            L.cons_dir[L.n_cons++] = 0;
+            cons_lv |= 1u << j;
+        }
+        if (p.out[v] & (1u << u)) {  // v -> u: v in in(phi(u))
+            L.cons_lvl[L.n_cons] = (uint8_t)j;
+            L.cons_dir[L.n_cons++] = 1;
+            cons_lv |= 1u << j;
+        }
+    }
+    uint32_t all_lv = (nlv_limit >= 32) ? ~0u : ((1u << nlv_limit) - 1);
+    L.inj = (uint8_t)(all_lv & ~cons_lv);
+    // Degree thresholds only prune when some arc of v goes to a later vertex.
+    bool out_later = (p.out[v] & later_mask) != 0;
+    bool in_later = (p.in[v] & later_mask) != 0;
+    L.dmin_out = out_later ? (uint32_t)p.dout(v) : 0;
+    L.dmin_in = in_later ? (uint32_t)p.din(v) : 0;
+    L.deg_check = (L.dmin_out || L.dmin_in) ? 1 : 0;
+}
+
+uint32_t cons_mask_bits(const LevelDesc& L, int c) { return (uint32_t)L.cons_lvl[c] * 2 + L.cons_dir[c]; }
+
+// True (and fills `extra`) when every constraint of src is a constraint of dst.
+bool cons_subset(const LevelDesc& src, const LevelDesc& dst, uint16_t& extra) {
+    uint32_t have = 0;
+    for (int c = 0; c < src.n_cons; c++) have |= 1u << cons_mask_bits(src, c);
+    uint32_t covered = 0;
+    extra = 0;
+    for (int c = 0; c < dst.n_cons; c++) {
+        uint32_t b = 1u << cons_mask_bits(dst, c);
+        if (have & b) covered |= b;
+        else extra |= (uint16_t)(1u << c);
+    }
+    return covered == have;
+}
+
+// Lower the degree filter of level r (and of the levels it reuses from, whose
+// candidates it inherits) so that no candidate a reuser needs is dropped.
+void weaken(PlanDesc& D, int r, uint32_t need_out, uint32_t need_in) {
+    LevelDesc& S = D.lvl[r];
+    S.dmin_out = std::min(S.dmin_out, need_out);
+    S.dmin_in = std::min(S.dmin_in, need_in);
+    S.deg_check = (S.dmin_out || S.dmin_in) ? 1 : 0;
+    if (S.reuse != kNoReuse) weaken(D, S.reuse, S.dmin_out, S.dmin_in);
+}
+
+void choose_reuse(PlanDesc& D, LevelDesc& L, int max_src_level, uint32_t need_out, uint32_t need_in) {
+    int best = -1;
+    uint16_t best_extra = 0;
+    for (int r = 1; r <= max_src_level; r++) {
+        LevelDesc& S = D.lvl[r];
+        uint16_t extra;
+        if (!cons_subset(S, L, extra)) continue;
+        bool weaker = S.dmin_out <= need_out && S.dmin_in <= need_in;
+        // a one-list source is only worth reusing when its filter is kept
+        if (!weaker && S.n_cons < 2) continue;
+        if (best < 0 || S.n_cons >= D.lvl[best].n_cons) {
+            best = r;
+            best_extra = extra;
+        }
+    }
+    if (best < 0) return;
+    // the source keeps only the degree filter every reuser can accept
+    weaken(D, best, need_out, need_in);
+    L.reuse = (uint8_t)best;
+    L.extra = best_extra;
+    D.seg_src |= 1u << best;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+std::string plan_json(const Pat& p, const PlanDesc& D, const CoverReport& cr, bool reduced,
+                      double cost) {
+    std::string s;
+    char buf[256];
+    auto arcstr = [&](int e) {
+        std::snprintf(buf, sizeof buf, "[%d,%d]", p.arcs[e].first, p.arcs[e].second);
+        return std::string(buf);
+    };
+    s += "{\"kind\":\"";
+    s += reduced ? "reduced" : "unreduced";
+    std::snprintf(buf, sizeof buf, "\",\"k\":%u,\"e\":%u,\"n_arcs\":%zu,\"root_vertex\":%d,", D.k, D.e,
+                  p.arcs.size(), D.order[0]);
+    s += buf;
+    std::snprintf(buf, sizeof buf, "\"root_dmin\":[%u,%u],\"est_cost\":%.6g,\"order\":[", D.root_dout,
+                  D.root_din, cost);
+    s += buf;
+    for (uint32_t i = 0; i < D.k; i++) {
+        std::snprintf(buf, sizeof buf, "%s%d", i ? "," : "", D.order[i]);
+        s += buf;
+    }
+    s += "],\"levels\":[";
+    auto lvl_json = [&](const LevelDesc& L) {
+        std::string o = "{\"cons\":[";
+        for (int c = 0; c < L.n_cons; c++) {
+            std::snprintf(buf, sizeof buf, "%s[%d,%d]", c ? "," : "", L.cons_lvl[c], L.cons_dir[c]);
+            o += buf;
+        }
+        std::snprintf(buf, sizeof buf, "],\"reuse\":%d,\"extra\":%u,\"inj\":%u,\"dmin\":[%u,%u]}",
+                      L.reuse == kNoReuse ? -1 : (int)L.reuse, (unsigned)L.extra, (unsigned)L.inj,
+                      L.dmin_out, L.dmin_in);
+        o += buf;
+        return o;
+    };
+    for (uint32_t i = 1; i < D.e; i++) {
+        if (i > 1) s += ",";
+        s += lvl_json(D.lvl[i]);
+    }
+    s += "],\"leaf_sigs\":[";
+    for (uint32_t g = 0; g < D.n_sig; g++) {
+        if (g) s += ",";
+        std::string o = lvl_json(D.sig[g]);
+        o.pop_back();
+        std::snprintf(buf, sizeof buf, ",\"mult\":%u,\"scan\":%u,\"implied\":%u,\"test\":%u}", D.sig_mult[g],
+                      D.sig_scan[g], D.sig_implied[g], D.sig_test[g]);
+        o += buf;
+        s += o;
+    }
+    std::snprintf(buf, sizeof buf, "],\"t\":%u,\"linear\":%u,\"seg_src\":%u,\"terms\":[", D.t, D.linear,
+                  D.seg_src);
+    s += buf;
+    for (uint32_t i = 0; i < D.n_terms; i++) {
+        std::snprintf(buf, sizeof buf, "%s{\"coef\":%d,\"masks\":[", i ? "," : "", D.terms[i].coef);
+        s += buf;
+        for (int b = 0; b < D.terms[i].nb; b++) {
+            std::snprintf(buf, sizeof buf, "%s%u", b ? "," : "", D.terms[i].mask[b]);
+            s += buf;
+        }
+        s += "]}";
+    }
+    s += "],\"arcs\":[";
+    for (size_t e = 0; e < p.arcs.size(); e++) s += (e ? "," : "") + arcstr((int)e);
+    s += "],\"inclusion_groups\":{\"in\":[";
+    for (int v = 0; v < p.k; v++) {
+        std::snprintf(buf, sizeof buf, "%s%d", v ? "," : "", cr.groups_in_rep[v]);
+        s += buf;
+    }
+    s += "],\"out\":[";
+    for (int v = 0; v < p.k; v++) {
+        std::snprintf(buf, sizeof buf, "%s%d", v ? "," : "", cr.groups_out_rep[v]);
+        s += buf;
+    }
+    s += "]},\"min_cover\":[";
+    for (size_t i = 0; i < cr.min_cover.size(); i++) s += (i ? "," : "") + arcstr(cr.min_cover[i]);
+    std::snprintf(buf, sizeof buf, "],\"min_cover_weight\":%.6g,\"greedy_cover\":[", cr.min_cover_weight);
+    s += buf;
+    for (size_t i = 0; i < cr.greedy_cover.size(); i++) s += (i ? "," : "") + arcstr(cr.greedy_cover[i]);
+    std::snprintf(buf, sizeof buf, "],\"removed_edges\":%zu}", p.arcs.size() - cr.min_cover.size());
+    s += buf;
+    return s;
+}
+
+int build_plan(uint32_t k, uint32_t n_arcs, const uint8_t* arcs, uint32_t flags, const GraphStats* gs,
+               PlanDesc& D, std::string& json, std::string& err) {
+    if (k < 2 || k > (uint32_t)kMaxK) {
+        err = "pattern must have 2..7 vertices";
+        return -2;
+    }
+    if (n_arcs == 0 || !arcs) {
+        err = "pattern has no arcs";
+        return -2;
+    }
+    Pat p;
+    p.k = (int)k;
+    for (uint32_t i = 0; i < n_arcs; i++) {
+        int a = arcs[2 * i], b = arcs[2 * i + 1];
+        if (a >= (int)k || b >= (int)k) {
+            err = "arc endpoint out of range";
+            return -2;
+        }
+        if (a == b) {
+            err = "self-loop arc in pattern";
+            return -2;
+        }
+        p.out[a] |= 1u << b;
+        p.in[b] |= 1u << a;
+    }
+    for (int a = 0; a < p.k; a++)
+        for (int b = 0; b < p.k; b++)
+            if (p.out[a] & (1u << b)) p.arcs.push_back({a, b});
+    uint32_t allv = (1u << k) - 1;
+    if (!connected(p, allv)) {
+        err = "pattern is not weakly connected";
+        return -2;
+    }
+    bool reduced = (flags & 0x3u) == 0x1u;
+    if ((flags & 0x3u) != 0x1u && (flags & 0x3u) != 0x2u) {
+        err = "exactly one of XM_PLAN_REDUCED / XM_PLAN_UNREDUCED";
+        return -1;
+    }
+    int forced = (int)((flags >> 8) & 0xFu) - 1;
+    if (forced >= p.k) {
+        err = "forced root vertex out of range";
+        return -1;
+    }
+    // Start vertex (Algorithm 1: maximal degree; ties: larger out-degree, then lowest id).
+    int start = 0;
+    for (int v = 1; v < p.k; v++)
+        if (p.deg(v) > p.deg(start) || (p.deg(v) == p.deg(start) && p.dout(v) > p.dout(start))) start = v;
+    if (forced >= 0) start = forced;
+
+    CoverReport cr = analyse_cover(p, gs, start);
+
+    // Choose the enumerated set / leaf group.
+    Cand best;
+    bool have = false;
+    if (reduced) {
+        for (uint32_t L = 0; L <= allv; L++) {
+            if (L & (1u << start)) continue;
+            if (L == 0) continue;
+            int t = popc(L);
+            if (t > kMaxLeaves || t >= p.k) continue;
+            bool indep = true;
+            for (int v = 0; v < p.k && indep; v++)
+                if ((L & (1u << v)) && (p.nbr(v) & L)) indep = false;
+            if (!indep) continue;
+            uint32_t E = allv & ~L;
+            if (!connected(p, E)) continue;
+            std::vector<LeafSig> sigs;
+            for (int v = 0; v < p.k; v++)
+                if (L & (1u << v)) {
+                    LeafSig s{p.in[v], p.out[v]};
+                    if (std::find(sigs.begin(), sigs.end(), s) == sigs.end()) sigs.push_back(s);
+                }
+            if ((int)sigs.size() > kMaxSig) continue;
+            Cand c;
+            c.order = enum_order(p, start, E);
+            for (int v = 0; v < p.k; v++)
+                if (L & (1u << v)) c.leaves.push_back(v);
+            c.cost = model_cost(p, c.order, (int)sigs.size(), gs);
+            if (!have || c.leaves.size() > best.leaves.size() ||
+                (c.leaves.size() == best.leaves.size() && c.cost < best.cost * (1 - 1e-9))) {
+                // check the term budget
+                std::sort(sigs.begin(), sigs.end());
+                std::vector<int> ls;
+                for (int v : c.leaves) {
+                    LeafSig s{p.in[v], p.out[v]};
+                    ls.push_back((int)(std::find(sigs.begin(), sigs.end(), s) - sigs.begin()));
+                }
+                std::vector<Term> tt;
+                if (!leaf_terms(ls, tt)) continue;
+                best = c;
+                have = true;
+            }
+        }
+    }
+    if (!have) {
+        // unreduced: all vertices in greedy order, the last one counted
+        std::vector<int> ord = enum_order(p, start, allv);
+        best.order.assign(ord.begin(), ord.end() - 1);
+        best.leaves = {ord.back()};
+        best.cost = model_cost(p, best.order, 1, gs);
+    }
+
+    std::memset(&D, 0, sizeof(D));
+    D.k = k;
+    D.e = (uint32_t)best.order.size();
+    std::vector<int> lvl_of(p.k, -1);
+    for (size_t i = 0; i < best.order.size(); i++) lvl_of[best.order[i]] = (int)i;
+    for (size_t i = 0; i < best.order.size(); i++) D.order[i] = (uint8_t)best.order[i];
+    D.root_dout = (uint32_t)p.dout(start);
+    D.root_din = (uint32_t)p.din(start);
+    uint32_t leaf_mask = 0;
+    for (int v : best.leaves) leaf_mask |= 1u << v;
+    for (uint32_t i = 1; i < D.e; i++) {
+        int v = best.order[i];
+        uint32_t later = leaf_mask;
+        for (size_t j = i + 1; j < best.order.size(); j++) later |= 1u << best.order[j];
+        fill_level(p, lvl_of, v, (int)i, later, D.lvl[i]);
+        if (reduced && i >= 2) choose_reuse(D, D.lvl[i], (int)i - 1, D.lvl[i].dmin_out, D.lvl[i].dmin_in);
+    }
+    // Leaf signatures.
+    std::vector<LeafSig> sigs;
+    for (int v : best.leaves) {
+        LeafSig s{p.in[v], p.out[v]};
+        if (std::find(sigs.begin(), sigs.end(), s) == sigs.end()) sigs.push_back(s);
+    }
+    std::sort(sigs.begin(), sigs.end());
+    D.n_sig = (uint32_t)sigs.size();
+    D.t = (uint32_t)best.leaves.size();
+    std::vector<int> leaf_sig;
+    for (int v : best.leaves) {
+        LeafSig s{p.in[v], p.out[v]};
+        int g = (int)(std::find(sigs.begin(), sigs.end(), s) - sigs.begin());
+        leaf_sig.push_back(g);
+        D.sig_mult[g]++;
+    }
+    for (uint32_t g = 0; g < D.n_sig; g++) {
+        // any leaf of this signature gives the same constraint set
+        int v = -1;
+        for (size_t i = 0; i < best.leaves.size(); i++)
+            if (leaf_sig[i] == (int)g) v = best.leaves[i];
+        fill_level(p, lvl_of, v, (int)D.e, 0u, D.sig[g]);
+        D.sig[g].dmin_out = D.sig[g].dmin_in = 0;  // implied by the constraints of a leaf
+        D.sig[g].deg_check = 0;
+        if (reduced && D.e >= 2)
+            choose_reuse(D, D.sig[g], (int)D.e - 1, (uint32_t)p.dout(v), (uint32_t)p.din(v));
+    }
+    for (uint32_t g = 0; g < D.n_sig; g++) {
+        uint8_t implied = 0;
+        bool scan = true;
+        for (uint32_t h = 0; h < D.n_sig; h++) {
+            if (sigs[h].subset_of(sigs[g])) implied |= (uint8_t)(1u << h);
+            if (h < g && sigs[h].subset_of(sigs[g])) scan = false;
+        }
+        D.sig_implied[g] = implied;
+        D.sig_scan[g] = scan ? 1 : 0;
+        D.sig_test[g] = (uint8_t)(((1u << D.n_sig) - 1) & ~implied);
+    }
+    std::vector<Term> terms;
+    leaf_terms(leaf_sig, terms);
+    D.n_terms = (uint32_t)terms.size();
+    for (size_t i = 0; i < terms.size(); i++) D.terms[i] = terms[i];
+    D.linear = (D.t == 1) ? 1 : 0;
+    for (size_t i = 0; i < best.leaves.size(); i++) D.order[D.e + i] = (uint8_t)best.leaves[i];
+    json = plan_json(p, D, cr, reduced, best.cost);
+    return 0;
+}
+
+}  // namespace xm

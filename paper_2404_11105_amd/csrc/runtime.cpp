@@ -1,0 +1,553 @@
+// runtime.cpp — the C ABI (include/xminer.h): graph residency, planning,
+// workspace layout and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/xminer.h"
+#include "kernels.h"
+#include "planner.h"
+
+using xm::PlanDesc;
+
+struct xm_graph_s {
+    int device = 0;
+    uint32_t n = 0, m = 0;
+    const uint32_t *out_off = nullptr, *out_adj = nullptr, *in_off = nullptr, *in_adj = nullptr;
+    bool owns_csr = false;
+    uint2* deg = nullptr;         // device, owned
+    uint32_t* hubs = nullptr;     // device, owned
+    uint32_t n_hubs = 0;
+    std::vector<uint32_t> hub_len;  // host: longest list of each hub (queue sizing)
+    uint32_t max_out = 0, max_in = 0;
+    int n_cu = 0;
+    size_t max_lds_block = 65536;
+    xm::GraphStats stats;
+};
+
+struct xm_plan_s {
+    PlanDesc desc;
+    std::string json;
+    std::mutex mu;
+    std::vector<void*> dev;  // per device copy of desc (lazy)
+};
+
+struct xm_exec_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return XM_ERR_HIP;
+}
+
+#define HIP_TRY(call, what)                         \
+    do {                                            \
+        hipError_t _e = (call);                     \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+// Device copy of a plan's descriptor (uploaded once per device).
+int plan_device_desc(xm_plan_t* p, int dev, const PlanDesc** out) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    if ((int)p->dev.size() <= dev) p->dev.resize(dev + 1, nullptr);
+    if (!p->dev[dev]) {
+        void* d = nullptr;
+        HIP_TRY(hipMalloc(&d, sizeof(PlanDesc)), "hipMalloc(plan)");
+        hipError_t e = hipMemcpy(d, &p->desc, sizeof(PlanDesc), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            return hip_fail(e, "hipMemcpy(plan)");
+        }
+        p->dev[dev] = d;
+    }
+    *out = static_cast<const PlanDesc*>(p->dev[dev]);
+    return XM_OK;
+}
+
+struct Layout {
+    uint32_t chunk, split, cap, waves_per_cu, n_waves, n_blocks, e_max, maxc;
+    bool nonlinear;
+    size_t off_ctl, off_flags, off_table, off_split, off_scratch, total;
+    uint32_t split_cap, wave_words, lds_words;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* plans,
+                const xm_count_opts* o, Layout& L) {
+    if (!g) return fail(XM_ERR_INVALID, "graph is NULL");
+    if (n_plans == 0 || !plans) return fail(XM_ERR_INVALID, "no plans");
+    if (o && o->struct_size != 0 && o->struct_size < sizeof(xm_count_opts))
+        return fail(XM_ERR_INVALID, "xm_count_opts.struct_size too small");
+    L.chunk = (o && o->chunk) ? o->chunk : 8;
+    L.split = (o && o->split) ? o->split : 512;
+    L.cap = (o && o->cap) ? o->cap : 4096;
+    L.waves_per_cu = (o && o->waves_per_cu) ? o->waves_per_cu : 16;
+    if (L.chunk > 64) return fail(XM_ERR_INVALID, "chunk must be <= 64");
+    if (L.split < xm::kHubMin) return fail(XM_ERR_INVALID, "split must be >= 64");
+    if (L.cap < L.split || L.cap < 64) return fail(XM_ERR_INVALID, "cap must be >= split and >= 64");
+    if (L.cap > (1u << 24)) return fail(XM_ERR_INVALID, "cap too large");
+    if (L.waves_per_cu < 4 || L.waves_per_cu > 32)
+        return fail(XM_ERR_INVALID, "waves_per_cu must be in 4..32");
+    uint32_t max_list = std::max(g->max_out, g->max_in);
+    if ((uint64_t)max_list * 64 >= (1ull << 32))
+        return fail(XM_ERR_INVALID, "adjacency lists too long for 32-bit window offsets");
+    L.e_max = 1;
+    L.maxc = 1;
+    L.nonlinear = false;
+    uint32_t splittable = 0;
+    for (uint32_t i = 0; i < n_plans; i++) {
+        if (!plans[i]) return fail(XM_ERR_INVALID, "plan is NULL");
+        const PlanDesc& D = plans[i]->desc;
+        L.e_max = std::max(L.e_max, D.e);
+        for (uint32_t l = 1; l < D.e; l++) L.maxc = std::max<uint32_t>(L.maxc, D.lvl[l].n_cons);
+        for (uint32_t s = 0; s < D.n_sig; s++) L.maxc = std::max<uint32_t>(L.maxc, D.sig[s].n_cons);
+        if (!D.linear) L.nonlinear = true;
+        if (D.e >= 2) splittable++;
+    }
+    L.n_waves = (uint32_t)g->n_cu * L.waves_per_cu;
+    L.n_waves = (L.n_waves + xm::kWavesPerBlock - 1) / xm::kWavesPerBlock * xm::kWavesPerBlock;
+    L.n_blocks = L.n_waves / xm::kWavesPerBlock;
+    L.lds_words = xm::lds_words_for(L.maxc, L.nonlinear);
+    if ((size_t)L.lds_words * 4 * xm::kWavesPerBlock > g->max_lds_block)
+        return fail(XM_ERR_INVALID, "plans need more LDS than a workgroup may use");
+    // split queue capacity: every splittable plan may split every hub root
+    uint64_t items = 0;
+    if (o && o->roots_dev) {
+        items = (uint64_t)o->n_roots * ((max_list + L.split - 1) / L.split);
+    } else {
+        for (uint32_t h : g->hub_len) items += (h + L.split - 1) / L.split;
+    }
+    items *= splittable;
+    if (items > 0xFFFFFFF0ull) return fail(XM_ERR_INVALID, "split queue too large; raise split");
+    L.split_cap = (uint32_t)std::max<uint64_t>(items, 1);
+    L.wave_words = L.e_max * xm::kLvlArrays * L.cap;
+    size_t off = 0;
+    L.off_ctl = off;
+    off = align256(off + xm::kCtlWords * 4);
+    L.off_flags = off;
+    off = align256(off + (size_t)n_plans * 4);
+    L.off_table = off;
+    off = align256(off + (size_t)n_plans * sizeof(PlanDesc));
+    L.off_split = off;
+    off = align256(off + (size_t)L.split_cap * 16);
+    L.off_scratch = off;
+    off = align256(off + (size_t)L.n_waves * L.wave_words * 4);
+    L.total = off;
+    return XM_OK;
+}
+
+int enqueue_count(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* plans,
+                  const xm_count_opts* o, void* ws, size_t ws_bytes, uint64_t* counts,
+                  int32_t* status, hipStream_t stream) {
+    Layout L;
+    int rc = make_layout(g, n_plans, plans, o, L);
+    if (rc) return rc;
+    if (!ws || ws_bytes < L.total) return fail(XM_ERR_WORKSPACE, "workspace missing or too small");
+    if (!counts || !status) return fail(XM_ERR_INVALID, "counts/status buffers are NULL");
+    if (o && (o->flags & XM_COUNT_STATS) && !o->stats_dev)
+        return fail(XM_ERR_INVALID, "XM_COUNT_STATS needs stats_dev");
+    if (o && o->roots_dev && o->n_roots == 0) return fail(XM_ERR_INVALID, "empty root subset");
+    int cur_dev = 0;
+    HIP_TRY(hipGetDevice(&cur_dev), "hipGetDevice");
+    if (cur_dev != g->device) return fail(XM_ERR_INVALID, "current device differs from the graph's");
+    char* base = static_cast<char*>(ws);
+    xm::KArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = {g->out_off, g->out_adj, g->in_off, g->in_adj, g->deg, g->n, 0};
+    a.plans = reinterpret_cast<const PlanDesc*>(base + L.off_table);
+    a.n_plans = n_plans;
+    a.chunk = L.chunk;
+    a.split = L.split;
+    a.cap = L.cap;
+    a.ctl = reinterpret_cast<uint32_t*>(base + L.off_ctl);
+    a.plan_flags = reinterpret_cast<uint32_t*>(base + L.off_flags);
+    a.split_items = reinterpret_cast<uint4*>(base + L.off_split);
+    a.split_cap = L.split_cap;
+    a.roots = (o && o->roots_dev) ? o->roots_dev : nullptr;
+    a.n_src = a.roots ? o->n_roots : g->n;
+    a.hubs = g->hubs;
+    a.n_hubs = g->n_hubs;
+    a.lds_words = L.lds_words;
+    a.maxc = L.maxc;
+    a.wave_words = L.wave_words;
+    a.scratch = reinterpret_cast<uint32_t*>(base + L.off_scratch);
+    a.counts = reinterpret_cast<unsigned long long*>(counts);
+    a.status = status;
+    a.cancel = o ? o->cancel_dev : nullptr;
+    bool stats = o && (o->flags & XM_COUNT_STATS);
+    a.stats = stats ? reinterpret_cast<unsigned long long*>(o->stats_dev) : nullptr;
+
+    std::vector<xm::InitArgs> inits;
+    for (uint32_t first = 0; first < n_plans; first += xm::kMaxPlansPerInit) {
+        xm::InitArgs ia;
+        std::memset(&ia, 0, sizeof(ia));
+        ia.table = reinterpret_cast<PlanDesc*>(base + L.off_table);
+        ia.first = first;
+        ia.count = std::min<uint32_t>(xm::kMaxPlansPerInit, n_plans - first);
+        for (uint32_t i = 0; i < ia.count; i++) {
+            const PlanDesc* d = nullptr;
+            int r2 = plan_device_desc(const_cast<xm_plan_t*>(plans[first + i]), g->device, &d);
+            if (r2) return r2;
+            ia.src[i] = d;
+        }
+        ia.n_plans = n_plans;
+        ia.zero_ctl = (first == 0) ? 1 : 0;
+        ia.ctl = a.ctl;
+        ia.plan_flags = a.plan_flags;
+        ia.counts = a.counts;
+        ia.stats = a.stats;
+        inits.push_back(ia);
+    }
+    hipEvent_t ev0 = o ? static_cast<hipEvent_t>(o->ev_kernel_start) : nullptr;
+    hipEvent_t ev1 = o ? static_cast<hipEvent_t>(o->ev_kernel_stop) : nullptr;
+    hipError_t e = xm::launch_count(inits.data(), (int)inits.size(), a, L.n_blocks, stats, stream, ev0, ev1);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return XM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* xm_version(void) { return "xminer-gfx950 0.1"; }
+
+const char* xm_last_error(void) { return g_err.c_str(); }
+
+const char* xm_strerror(int code) {
+    switch (code) {
+        case XM_OK: return "ok";
+        case XM_ERR_INVALID: return "invalid argument";
+        case XM_ERR_PATTERN: return "pattern rejected";
+        case XM_ERR_OOM: return "out of memory";
+        case XM_ERR_HIP: return "HIP runtime error";
+        case XM_ERR_OVERFLOW: return "count exceeded 2^128-1";
+        case XM_ERR_WORKSPACE: return "workspace too small";
+        case XM_ERR_CANCELLED: return "cancelled";
+        case XM_ERR_GRAPH: return "graph failed validation";
+        default: return "unknown status";
+    }
+}
+
+int xm_load_graph(uint32_t n, uint32_t m, const uint32_t* out_off, const uint32_t* out_adj,
+                  const uint32_t* in_off, const uint32_t* in_adj, uint32_t flags, void* hip_stream,
+                  xm_graph_t** out) {
+    if (!out) return fail(XM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (n == 0 || n >= 0xFFFFFFFFu) return fail(XM_ERR_INVALID, "n must be in 1..2^32-2");
+    if (!out_off || !in_off || (m > 0 && (!out_adj || !in_adj)))
+        return fail(XM_ERR_INVALID, "CSR array is NULL");
+    bool dev_mem = (flags & XM_MEM_DEVICE) != 0, host_mem = (flags & XM_MEM_HOST) != 0;
+    if (dev_mem == host_mem) return fail(XM_ERR_INVALID, "set exactly one of XM_MEM_DEVICE / XM_MEM_HOST");
+    if (flags & ~(XM_MEM_DEVICE | XM_MEM_HOST | XM_VALIDATE)) return fail(XM_ERR_INVALID, "unknown flag");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    xm_graph_t* g = new (std::nothrow) xm_graph_s;
+    if (!g) return fail(XM_ERR_OOM, "host allocation");
+    g->n = n;
+    g->m = m;
+    HIP_TRY(hipGetDevice(&g->device), "hipGetDevice");
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, g->device), "hipGetDeviceProperties");
+    g->n_cu = prop.multiProcessorCount;
+    g->max_lds_block = prop.sharedMemPerBlock;
+    // host copies of the offsets (and lists when validating)
+    std::vector<uint32_t> ho(n + 1), hi(n + 1), hoa, hia;
+    auto to_host = [&](std::vector<uint32_t>& dst, const uint32_t* src, size_t cnt) -> hipError_t {
+        dst.resize(cnt);
+        if (cnt == 0) return hipSuccess;
+        if (host_mem) {
+            std::memcpy(dst.data(), src, cnt * 4);
+            return hipSuccess;
+        }
+        return hipMemcpy(dst.data(), src, cnt * 4, hipMemcpyDeviceToHost);
+    };
+    auto cleanup = [&]() {
+        if (g->owns_csr) {
+            (void)hipFree((void*)g->out_off);
+            (void)hipFree((void*)g->out_adj);
+            (void)hipFree((void*)g->in_off);
+            (void)hipFree((void*)g->in_adj);
+        }
+        if (g->deg) (void)hipFree(g->deg);
+        if (g->hubs) (void)hipFree(g->hubs);
+        delete g;
+    };
+    hipError_t e;
+    if ((e = to_host(ho, out_off, n + 1)) != hipSuccess || (e = to_host(hi, in_off, n + 1)) != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "copy offsets");
+    }
+    if (ho[0] != 0 || hi[0] != 0 || ho[n] != m || hi[n] != m) {
+        cleanup();
+        return fail(XM_ERR_GRAPH, "offsets must start at 0 and end at m");
+    }
+    for (uint32_t v = 0; v < n; v++)
+        if (ho[v + 1] < ho[v] || hi[v + 1] < hi[v]) {
+            cleanup();
+            return fail(XM_ERR_GRAPH, "offsets must be non-decreasing");
+        }
+    if (flags & XM_VALIDATE) {
+        if ((e = to_host(hoa, out_adj, m)) != hipSuccess || (e = to_host(hia, in_adj, m)) != hipSuccess) {
+            cleanup();
+            return hip_fail(e, "copy lists");
+        }
+        std::vector<uint32_t> cnt(n, 0);
+        for (uint32_t u = 0; u < n; u++)
+            for (uint32_t k = ho[u]; k < ho[u + 1]; k++) {
+                uint32_t v = hoa[k];
+                if (v >= n || v == u || (k > ho[u] && hoa[k - 1] >= v)) {
+                    cleanup();
+                    return fail(XM_ERR_GRAPH, "out-lists must be sorted, distinct, in range, loop-free");
+                }
+                cnt[v]++;
+            }
+        for (uint32_t v = 0; v < n; v++)
+            if (cnt[v] != hi[v + 1] - hi[v]) {
+                cleanup();
+                return fail(XM_ERR_GRAPH, "in-CSR is not the transpose of the out-CSR");
+            }
+        std::vector<uint32_t> fill(n, 0);
+        for (uint32_t u = 0; u < n; u++)
+            for (uint32_t k = ho[u]; k < ho[u + 1]; k++) {
+                uint32_t v = hoa[k];
+                if (hia[hi[v] + fill[v]++] != u) {
+                    cleanup();
+                    return fail(XM_ERR_GRAPH, "in-CSR is not the transpose of the out-CSR");
+                }
+            }
+    }
+    if (host_mem) {
+        void* p[4] = {nullptr, nullptr, nullptr, nullptr};
+        size_t sz[4] = {(size_t)(n + 1) * 4, (size_t)std::max<uint32_t>(m, 1) * 4, (size_t)(n + 1) * 4,
+                        (size_t)std::max<uint32_t>(m, 1) * 4};
+        const void* src[4] = {out_off, out_adj, in_off, in_adj};
+        size_t cp[4] = {(size_t)(n + 1) * 4, (size_t)m * 4, (size_t)(n + 1) * 4, (size_t)m * 4};
+        g->owns_csr = true;
+        for (int i = 0; i < 4; i++) {
+            if ((e = hipMalloc(&p[i], sz[i])) != hipSuccess) {
+                for (int j = 0; j < i; j++) (void)hipFree(p[j]);
+                g->owns_csr = false;
+                cleanup();
+                return fail(XM_ERR_OOM, "hipMalloc(csr)");
+            }
+        }
+        g->out_off = (uint32_t*)p[0];
+        g->out_adj = (uint32_t*)p[1];
+        g->in_off = (uint32_t*)p[2];
+        g->in_adj = (uint32_t*)p[3];
+        for (int i = 0; i < 4; i++)
+            if (cp[i] && (e = hipMemcpyAsync(p[i], src[i], cp[i], hipMemcpyHostToDevice, stream)) != hipSuccess) {
+                cleanup();
+                return hip_fail(e, "hipMemcpyAsync(csr)");
+            }
+    } else {
+        g->out_off = out_off;
+        g->out_adj = out_adj;
+        g->in_off = in_off;
+        g->in_adj = in_adj;
+    }
+    // degrees, hub candidates and statistics
+    std::vector<uint2> deg(n);
+    std::vector<std::pair<uint32_t, uint32_t>> hubs;
+    uint64_t ge_out[8] = {0}, ge_in[8] = {0};
+    for (uint32_t v = 0; v < n; v++) {
+        uint32_t dout = ho[v + 1] - ho[v], din = hi[v + 1] - hi[v];
+        deg[v] = make_uint2(dout, din);
+        g->max_out = std::max(g->max_out, dout);
+        g->max_in = std::max(g->max_in, din);
+        uint32_t mx = std::max(dout, din);
+        if (mx > xm::kHubMin) hubs.push_back({mx, v});
+        for (int t = 0; t < 8; t++) {
+            ge_out[t] += dout >= (uint32_t)t;
+            ge_in[t] += din >= (uint32_t)t;
+        }
+    }
+    std::sort(hubs.begin(), hubs.end(), [](auto& x, auto& y) { return x.first > y.first || (x.first == y.first && x.second < y.second); });
+    g->n_hubs = (uint32_t)hubs.size();
+    g->hub_len.resize(hubs.size());
+    std::vector<uint32_t> hub_ids(std::max<size_t>(hubs.size(), 1), 0);
+    for (size_t i = 0; i < hubs.size(); i++) {
+        g->hub_len[i] = hubs[i].first;
+        hub_ids[i] = hubs[i].second;
+    }
+    g->stats.n = n;
+    g->stats.m = m;
+    for (int t = 0; t < 8; t++) {
+        g->stats.frac_out_ge[t] = (double)ge_out[t] / n;
+        g->stats.frac_in_ge[t] = (double)ge_in[t] / n;
+    }
+    if ((e = hipMalloc(&g->deg, (size_t)n * sizeof(uint2))) != hipSuccess ||
+        (e = hipMalloc(&g->hubs, hub_ids.size() * 4)) != hipSuccess) {
+        cleanup();
+        return fail(XM_ERR_OOM, "hipMalloc(degrees)");
+    }
+    if ((e = hipMemcpyAsync(g->deg, deg.data(), (size_t)n * sizeof(uint2), hipMemcpyHostToDevice, stream)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(g->hubs, hub_ids.data(), hub_ids.size() * 4, hipMemcpyHostToDevice, stream)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(stream)) != hipSuccess) {
+        cleanup();
+        return hip_fail(e, "upload degrees");
+    }
+    *out = g;
+    return XM_OK;
+}
+
+int xm_free_graph(xm_graph_t* g) {
+    if (!g) return XM_OK;
+    if (g->owns_csr) {
+        (void)hipFree((void*)g->out_off);
+        (void)hipFree((void*)g->out_adj);
+        (void)hipFree((void*)g->in_off);
+        (void)hipFree((void*)g->in_adj);
+    }
+    if (g->deg) (void)hipFree(g->deg);
+    if (g->hubs) (void)hipFree(g->hubs);
+    delete g;
+    return XM_OK;
+}
+
+int xm_graph_info(const xm_graph_t* g, uint32_t* n, uint32_t* m, uint32_t* max_out, uint32_t* max_in) {
+    if (!g) return fail(XM_ERR_INVALID, "graph is NULL");
+    if (n) *n = g->n;
+    if (m) *m = g->m;
+    if (max_out) *max_out = g->max_out;
+    if (max_in) *max_in = g->max_in;
+    return XM_OK;
+}
+
+int xm_plan(uint32_t k, uint32_t n_arcs, const uint8_t* arcs, uint32_t flags, const xm_graph_t* g,
+            xm_plan_t** out) {
+    if (!out) return fail(XM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (flags & ~(0x3u | 0xF00u)) return fail(XM_ERR_INVALID, "unknown plan flag");
+    xm_plan_t* p = new (std::nothrow) xm_plan_s;
+    if (!p) return fail(XM_ERR_OOM, "host allocation");
+    std::string err;
+    int rc = xm::build_plan(k, n_arcs, arcs, flags, g ? &g->stats : nullptr, p->desc, p->json, err);
+    if (rc) {
+        delete p;
+        return fail(rc == -1 ? XM_ERR_INVALID : XM_ERR_PATTERN, err);
+    }
+    *out = p;
+    return XM_OK;
+}
+
+int xm_plan_describe(const xm_plan_t* p, char* json, size_t cap, size_t* needed) {
+    if (!p) return fail(XM_ERR_INVALID, "plan is NULL");
+    if (needed) *needed = p->json.size() + 1;
+    if (!json || cap < p->json.size() + 1) return fail(XM_ERR_INVALID, "buffer too small");
+    std::memcpy(json, p->json.c_str(), p->json.size() + 1);
+    return XM_OK;
+}
+
+int xm_plan_root_vertex(const xm_plan_t* p) {
+    if (!p) return fail(XM_ERR_INVALID, "plan is NULL");
+    return p->desc.order[0];
+}
+
+int xm_free_plan(xm_plan_t* p) {
+    if (!p) return XM_OK;
+    for (size_t d = 0; d < p->dev.size(); d++)
+        if (p->dev[d]) {
+            int cur = 0;
+            (void)hipGetDevice(&cur);
+            (void)hipSetDevice((int)d);
+            (void)hipFree(p->dev[d]);
+            (void)hipSetDevice(cur);
+        }
+    delete p;
+    return XM_OK;
+}
+
+size_t xm_workspace_size(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* plans,
+                         const xm_count_opts* opts) {
+    Layout L;
+    if (make_layout(g, n_plans, plans, opts, L)) return 0;
+    return L.total;
+}
+
+int xm_count(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* plans, const xm_count_opts* opts,
+             void* workspace, size_t ws_bytes, uint64_t* counts_dev, int32_t* status_dev, void* hip_stream) {
+    return enqueue_count(g, n_plans, plans, opts, workspace, ws_bytes, counts_dev, status_dev,
+                         static_cast<hipStream_t>(hip_stream));
+}
+
+int xm_count_capture(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* plans,
+                     const xm_count_opts* opts, void* workspace, size_t ws_bytes, uint64_t* counts_dev,
+                     int32_t* status_dev, void* hip_stream, xm_exec_t** out) {
+    if (!out) return fail(XM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    Layout L;
+    int rc = make_layout(g, n_plans, plans, opts, L);
+    if (rc) return rc;
+    if (!hip_stream) return fail(XM_ERR_INVALID, "capture needs a non-null stream");
+    // plan uploads happen outside the capture
+    for (uint32_t i = 0; i < n_plans; i++) {
+        const PlanDesc* d = nullptr;
+        rc = plan_device_desc(const_cast<xm_plan_t*>(plans[i]), g->device, &d);
+        if (rc) return rc;
+    }
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    xm_exec_t* x = new (std::nothrow) xm_exec_s;
+    if (!x) return fail(XM_ERR_OOM, "host allocation");
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        delete x;
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    rc = enqueue_count(g, n_plans, plans, opts, workspace, ws_bytes, counts_dev, status_dev, s);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(s, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        delete x;
+        return rc;
+    }
+    if (e != hipSuccess) {
+        delete x;
+        return hip_fail(e, "hipStreamEndCapture");
+    }
+    x->graph = graph;
+    e = hipGraphInstantiate(&x->exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        delete x;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    *out = x;
+    return XM_OK;
+}
+
+int xm_exec_launch(xm_exec_t* x, void* hip_stream) {
+    if (!x) return fail(XM_ERR_INVALID, "exec is NULL");
+    HIP_TRY(hipGraphLaunch(x->exec, static_cast<hipStream_t>(hip_stream)), "hipGraphLaunch");
+    return XM_OK;
+}
+
+int xm_free_exec(xm_exec_t* x) {
+    if (!x) return XM_OK;
+    if (x->exec) (void)hipGraphExecDestroy(x->exec);
+    if (x->graph) (void)hipGraphDestroy(x->graph);
+    delete x;
+    return XM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,174 @@
+"""GPU parity: the HIP path through the C ABI against the oracle, bit-exact.
+
+Every expected value comes from the oracle (at test time, or stored under
+tests/golden/ by make_golden.py, which calls only the oracle) or from a
+closed form written out in tests/pins.py.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import xmgen
+from tests import pins
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+from tests.cases import NAMED_ALL as NAMED
+
+
+@pytest.fixture(scope="module")
+def xa():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2404_11105_amd as xa
+    return xa
+
+
+def run(xa, g, pats, reduced=True, G=None, **opts):
+    G = G or xa.Graph(g)
+    plans = [xa.Plan(p, reduced=reduced, graph=G) for p in pats]
+    c = xa.Counter(G, plans, **opts)
+    c.run()
+    counts, status = c.results()
+    assert all(s == 0 for s in status), status
+    return counts
+
+
+def banner(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def golden_case(name):
+    from tests.cases import CASES
+    gold = json.load(open(os.path.join(HERE, "golden", "cases.json")))[name]
+    c = CASES[name]
+    g = c["graph"]()
+    pats = c["patterns"]()
+    assert [list(map(list, p.arcs)) for p in pats] == gold["patterns"], "case drifted from its golden"
+    return c, g, pats, [int(x) for x in gold["counts"]]
+
+
+def test_config1_bifan_reduced(xa):
+    banner("uniform 2000/20000 seed 0, bifan reduced")
+    g = xmgen.uniform_digraph(2000, 20000, 0)
+    pat = xmgen.named("bifan")
+    assert run(xa, g, [pat]) == [oracle.count(g, pat)]
+
+
+@pytest.mark.parametrize("case", ["uniform2000_named", "rmat11_named", "rand_uniform300", "rand_rmat8"])
+@pytest.mark.parametrize("reduced", [True, False])
+def test_cases_vs_oracle(xa, case, reduced):
+    banner(f"{case} reduced={reduced}")
+    _, g, pats, want = golden_case(case)
+    assert run(xa, g, pats, reduced=reduced) == want
+
+
+@pytest.mark.parametrize("tune", [dict(chunk=1, split=64, cap=64), dict(chunk=64, split=64, cap=128),
+                                  dict(chunk=7, split=100, cap=4096, waves_per_cu=4)])
+def test_tunings_exercise_splits_and_partial_windows(xa, tune):
+    banner(f"rmat 11 tunings {tune}")
+    _, g, pats, want = golden_case("tune_rmat11")
+    assert run(xa, g, pats, reduced=True, **tune) == want
+    assert run(xa, g, pats, reduced=False, **tune) == want
+
+
+def test_batched_equals_plain(xa):
+    banner("batched vs plain, 24 random patterns on rmat 10")
+    _, g, pats, want = golden_case("batch_rmat10")
+    G = xa.Graph(g)
+    batched = run(xa, g, pats, G=G)
+    plain = [run(xa, g, [p], G=G)[0] for p in pats]
+    assert batched == plain == want
+
+
+def test_tiny_and_degenerate_graphs(xa):
+    banner("tiny and degenerate graphs")
+    cases = [xmgen.complete_digraph(2), xmgen.complete_digraph(5), xmgen.from_arcs(3, [0], [1]),
+             xmgen.from_arcs(6, [], []), xmgen.star_hub(3, extra_nodes=2)]
+    for g in cases:
+        pats = [xmgen.named(n) for n in ["arc", "pair2", "ffl", "c3", "bifan", "outstar3", "c4"]]
+        want = [oracle.count(g, p) for p in pats]
+        assert run(xa, g, pats) == want, g.name
+        assert run(xa, g, pats, reduced=False) == want, g.name
+
+
+def test_complete_digraph_closed_form(xa):
+    banner("complete digraph 9: n!/(n-k)!")
+    g = xmgen.complete_digraph(9)
+    pats = [xmgen.named(n) for n in NAMED] + [xmgen.random_pattern(k, 77 + k) for k in range(3, 8)]
+    want = [pins.complete_count(9, p.k) for p in pats]
+    assert run(xa, g, pats) == want
+    assert run(xa, g, pats, reduced=False) == want
+
+
+def test_u128_star_hub_closed_form(xa):
+    banner("out-star hub D=100000, 5 leaves: falling factorial > 2^64")
+    D = 100000
+    g = xmgen.star_hub(D)
+    pat = xmgen.named("outstar5")
+    want = pins.falling(D, 5)
+    assert want > 2 ** 64
+    assert run(xa, g, [pat]) == [want]
+    want3 = pins.falling(D, 3)
+    assert run(xa, g, [xmgen.named("outstar3")]) == [want3]
+
+
+def test_root_subset_partial_sums(xa):
+    banner("root subset partial sums, rmat 11")
+    c, g, pats, want = golden_case("subset_rmat11")
+    G = xa.Graph(g)
+    for pat, rv, w in zip(pats, c["root_vertex"], want):
+        for reduced in (True, False):
+            p = xa.Plan(pat, reduced=reduced, graph=G, root_vertex=rv)
+            cnt = xa.Counter(G, [p], roots=c["roots"])
+            cnt.run()
+            got, st = cnt.results()
+            assert got == [w] and st == [0], (pat.name, reduced)
+
+
+def test_stats_mode_same_counts(xa):
+    banner("stats mode")
+    g = xmgen.rmat(9, seed=2)
+    G = xa.Graph(g)
+    pats = [xmgen.named("bifan"), xmgen.named("c4")]
+    plans = [xa.Plan(p, graph=G) for p in pats]
+    c = xa.Counter(G, plans, stats=True)
+    c.run()
+    counts, _ = c.results()
+    assert counts == [oracle.count(g, p) for p in pats]
+    st = c.stats_list()
+    assert all(s["elements"] > 0 and s["fetches"] > 0 and s["root_tasks"] > 0 for s in st)
+
+
+def test_graph_replay_matches_eager(xa):
+    import torch
+    banner("hip graph capture and replays")
+    _, g, pats, want = golden_case("replay_rmat10")
+    G = xa.Graph(g)
+    plans = [xa.Plan(p, graph=G) for p in pats]
+    s = torch.cuda.Stream()
+    c = xa.Counter(G, plans)
+    c.capture(s)
+    for _ in range(4):
+        c.run(s)
+        s.synchronize()
+        got, st = c.results()
+        assert got == want and st == [0] * len(pats)
+        torch.zeros(1000, device="cuda").sum().item()  # eager work between replays
+
+
+def test_config2_full_size(xa):
+    banner("rmat 16 full size, 4 patterns x reduced/unreduced vs stored oracle counts")
+    gold = json.load(open(os.path.join(HERE, "golden", "rmat16.json")))["counts"]
+    g = xmgen.rmat(16, seed=0)
+    G = xa.Graph(g)
+    names = list(gold)
+    pats = [xmgen.named(n) for n in names]
+    want = [int(gold[n]) for n in names]
+    assert run(xa, g, pats, G=G, reduced=True) == want
+    assert run(xa, g, pats, G=G, reduced=False) == want
