@@ -42,21 +42,26 @@ def lib_hash() -> str:
 
 
 def timed_steps(counter, stream, steps, warmup):
+    """Wall time per step, and the GPU time of each launch from HIP events
+    recorded on the launch stream around it (these also cover the three
+    microsecond-scale set-up/status kernels next to the count kernel)."""
     import torch
     for _ in range(warmup):
         counter.run(stream)
     stream.synchronize()
-    kms = []
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for e0, e1 in evs:
+        e0.record(stream)
         counter.run(stream)
+        e1.record(stream)
         stream.synchronize()
-        if counter.events is not None:
-            kms.append(counter.kernel_ms())
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps * 1e3
-    return wall, (sum(kms) / len(kms) if kms else None)
+    gpu = sum(e0.elapsed_time(e1) for e0, e1 in evs) / steps
+    return wall, gpu
 
 
 def timed_plain(counters, stream, steps, warmup):
@@ -119,6 +124,20 @@ def traffic_from_profile(n_launch_plans):
         return None
 
 
+def copy_probe(mib: int, reps: int):
+    """Plain device-to-device copies of `mib` MiB: reads and writes are known
+    exactly, so the HBM counters of the same run calibrate the count kernel's."""
+    import torch
+    torch.cuda.set_device(0)
+    n = mib * (1 << 20) // 4
+    a = torch.arange(n, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 4, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,7 +149,12 @@ def main():
     ap.add_argument("--split", type=int, default=0)
     ap.add_argument("--cap", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run plain device copies of this size (counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe_mib:
+        copy_probe(args.copy_probe_mib, args.steps)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -142,7 +166,7 @@ def main():
     import torch
 
     import xmgen
-    from paper_2404_11105_amd import Counter, Graph, Plan
+    from paper_2404_11105_amd import Counter, Graph, Plan, plan_work
 
     torch.cuda.set_device(0)
     log("[bench] generating R-MAT scale 16")
@@ -154,24 +178,20 @@ def main():
     unred = [Plan(p, reduced=False, graph=G) for p in pats]
     s = torch.cuda.Stream()
 
-    # untimed work statistics of the batched reduced launch
-    log("[bench] stats pass")
-    cs = Counter(G, red, stats=True, **tune)
-    cs.run(s)
-    s.synchronize()
-    counts_stats, _ = cs.results()
-    st = cs.stats_list()
+    # algorithmic work of the four reduced plans (host walk, untimed)
+    log("[bench] algorithmic work (host walk)")
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    st = [plan_work(g, p, threads=threads) for p in red]
     E = sum(x["elements"] for x in st)
     F = sum(x["fetches"] for x in st)
     B_alg = 4 * E + 8 * F + 8 * g.n * len(pats)
 
     log("[bench] batched reduced (HIP graph)")
-    cb = Counter(G, red, kernel_events=True, stream=s, **tune)
+    cb = Counter(G, red, **tune)
     cb.capture(s)
     ms_step, kern_ms = timed_steps(cb, s, args.steps, args.warmup)
     counts, status = cb.results()
     assert status == [0] * len(pats), status
-    assert counts == counts_stats
 
     extras = {}
     if not args.no_extras:
@@ -180,14 +200,11 @@ def main():
         ms_plain = timed_plain(plain, s, args.steps, args.warmup)
         assert [c.results()[0][0] for c in plain] == counts
         log("[bench] batched unreduced")
-        cu = Counter(G, unred, kernel_events=True, stream=s, **tune)
+        cu = Counter(G, unred, **tune)
         cu.capture(s)
         ms_unred, kern_unred = timed_steps(cu, s, max(3, args.steps // 4), 1)
         assert cu.results()[0] == counts
-        cus = Counter(G, unred, stats=True, **tune)
-        cus.run(s)
-        s.synchronize()
-        E_un = sum(x["elements"] for x in cus.stats_list())
+        E_un = sum(plan_work(g, p, threads=threads)["elements"] for p in unred)
         extras = {"plain_ms_per_step": round(ms_plain, 4),
                   "batched_vs_plain_speedup": round(ms_plain / ms_step, 3),
                   "unreduced_ms_per_step": round(ms_unred, 4),
@@ -231,6 +248,7 @@ def main():
         "counts": [str(c) for c in counts],
         "counts_match_oracle": gold_ok,
         "kernel_ms": round(kern_ms, 4),
+        "kernel_ms_note": "HIP events on the launch stream around each HIP-graph replay",
         "elements_intersected": E,
         "list_fetches": F,
         "elements_per_s": E / (kern_ms / 1e3),

@@ -125,6 +125,19 @@ int xm_plan_describe(const xm_plan_t* p, char* json, size_t cap, size_t* needed)
 int xm_plan_root_vertex(const xm_plan_t* p);
 int xm_free_plan(xm_plan_t* p);
 
+/* Algorithmic work of plan p on a graph given as HOST CSR arrays (same rules
+ * as xm_load_graph): a host computation for statistics only, it returns no
+ * count.  It walks the plan's partial matches and sums, per partial match
+ * and level, the length of the base list and of every list probed for
+ * membership (with section 5.2's reuse the reused candidate set is the
+ * base).  out[0] = adjacency elements intersected, out[1] = list fetches,
+ * out[2] = partial matches of the enumerated levels, out[3] = roots that
+ * pass the start vertex's degree constraint.  roots (nullable, host array)
+ * limits the start vertex's images.  threads: host worker threads (0 = 1). */
+int xm_plan_work(uint32_t n, const uint32_t* out_off, const uint32_t* out_adj,
+                 const uint32_t* in_off, const uint32_t* in_adj, const xm_plan_t* p,
+                 const uint32_t* roots, uint32_t n_roots, uint32_t threads, uint64_t out[4]);
+
 /* ----------------------------------------------------------------------------
  * Counting (Algorithm 2; sections 5.2-5.3).
  *
@@ -143,14 +156,14 @@ int xm_free_plan(xm_plan_t* p);
  * opts (nullable): see xm_count_opts.  Fields left 0 take defaults.
  * Returns after enqueueing; results are ready when hip_stream completes.
  * ------------------------------------------------------------------------- */
-#define XM_COUNT_STATS 0x1u /* also write per-plan work statistics (slower) */
-
 typedef struct xm_count_opts {
     uint32_t struct_size;   /* sizeof(xm_count_opts) */
-    uint32_t flags;         /* XM_COUNT_STATS */
-    uint32_t chunk;         /* roots taken per work grab (default 8) */
-    uint32_t split;         /* first-level candidate lists longer than this are
-                               split into stealable sub-ranges (default 512) */
+    uint32_t flags;         /* reserved, must be 0 */
+    uint32_t chunk;         /* roots taken per work grab (default 4, <= 64) */
+    uint32_t split;         /* a root whose first-level candidate list has L1
+                               entries is split into stealable sub-ranges of
+                               min(split, split_work / L1) entries (at least 1)
+                               when L1 exceeds that size (default 64, >= 64) */
     uint32_t cap;           /* per-level candidate buffer entries (default 4096,
                                at least split) */
     uint32_t waves_per_cu;  /* resident waves per compute unit (default 16) */
@@ -163,11 +176,13 @@ typedef struct xm_count_opts {
     /* cancel flag: device int32; when it becomes nonzero, waves stop taking
        new work and the status of unfinished plans is XM_ERR_CANCELLED. */
     const int32_t* cancel_dev;
-    /* XM_COUNT_STATS: device buffer of 4*n_plans uint64 per plan:
-       [0] adjacency elements intersected (base list + every probed list, full
-       lengths), [1] list fetches, [2] partial matches materialised,
-       [3] root tasks. */
-    uint64_t* stats_dev;
+    uint32_t split_work;    /* see split (default 8192, >= 4096) */
+    /* single-leaf intersections whose two lists are both at least merge_min
+       long (default 0xFFFFFFFF: off) and within merge_ratio of each
+       other (default 16) are counted by a wave-cooperative merge instead of
+       per-element binary search. */
+    uint32_t merge_min;
+    uint32_t merge_ratio;
     /* Profiling (nullable hipEvent_t): recorded on hip_stream immediately
        before and after the count kernel itself, so its duration excludes the
        small set-up and status kernels. */

@@ -27,7 +27,6 @@ XM_MEM_HOST = 0x2
 XM_VALIDATE = 0x4
 XM_PLAN_REDUCED = 0x1
 XM_PLAN_UNREDUCED = 0x2
-XM_COUNT_STATS = 0x1
 
 
 def XM_PLAN_ROOT(v: int) -> int:
@@ -46,7 +45,9 @@ class XmCountOpts(ctypes.Structure):
         ("n_roots", ctypes.c_uint32),
         ("reserved0", ctypes.c_uint32),
         ("cancel_dev", ctypes.c_void_p),
-        ("stats_dev", ctypes.c_void_p),
+        ("split_work", ctypes.c_uint32),
+        ("merge_min", ctypes.c_uint32),
+        ("merge_ratio", ctypes.c_uint32),
         ("ev_kernel_start", ctypes.c_void_p),
         ("ev_kernel_stop", ctypes.c_void_p),
     ]
@@ -60,7 +61,7 @@ class XminerError(RuntimeError):
 
 EXPORTS = [
     "xm_load_graph", "xm_free_graph", "xm_graph_info", "xm_plan", "xm_plan_describe",
-    "xm_plan_root_vertex", "xm_free_plan", "xm_workspace_size", "xm_count", "xm_count_capture",
+    "xm_plan_root_vertex", "xm_free_plan", "xm_plan_work", "xm_workspace_size", "xm_count", "xm_count_capture",
     "xm_exec_launch", "xm_free_exec", "xm_strerror", "xm_last_error", "xm_version",
 ]
 
@@ -83,6 +84,7 @@ def lib():
         L.xm_plan_describe.argtypes = [P, ctypes.c_char_p, SZ, ctypes.POINTER(SZ)]
         L.xm_plan_root_vertex.argtypes = [P]
         L.xm_free_plan.argtypes = [P]
+        L.xm_plan_work.argtypes = [U32, P, P, P, P, P, P, U32, U32, P]
         L.xm_workspace_size.argtypes = [P, U32, P, P]
         L.xm_workspace_size.restype = SZ
         L.xm_count.argtypes = [P, U32, P, P, P, SZ, P, P, P]
@@ -94,7 +96,8 @@ def lib():
         L.xm_last_error.restype = ctypes.c_char_p
         L.xm_version.restype = ctypes.c_char_p
         for name in ["xm_load_graph", "xm_free_graph", "xm_graph_info", "xm_plan",
-                     "xm_plan_describe", "xm_plan_root_vertex", "xm_free_plan", "xm_count",
+                     "xm_plan_describe", "xm_plan_root_vertex", "xm_free_plan", "xm_plan_work",
+                     "xm_count",
                      "xm_count_capture", "xm_exec_launch", "xm_free_exec"]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L

@@ -117,19 +117,17 @@ def describe_plan(pattern, reduced: bool = True) -> dict:
     return Plan(pattern, reduced).describe()
 
 
-def make_opts(chunk=0, split=0, cap=0, waves_per_cu=0, roots=None, cancel=None, stats=None,
-              events=None):
+def make_opts(chunk=0, split=0, cap=0, waves_per_cu=0, roots=None, cancel=None, events=None,
+              merge_min=0, merge_ratio=0, split_work=0):
     o = _lib.XmCountOpts()
     o.struct_size = ctypes.sizeof(_lib.XmCountOpts)
     o.chunk, o.split, o.cap, o.waves_per_cu = chunk, split, cap, waves_per_cu
+    o.merge_min, o.merge_ratio, o.split_work = merge_min, merge_ratio, split_work
     if roots is not None:
         o.roots_dev = roots.data_ptr()
         o.n_roots = roots.numel()
     if cancel is not None:
         o.cancel_dev = cancel.data_ptr()
-    if stats is not None:
-        o.stats_dev = stats.data_ptr()
-        o.flags |= _lib.XM_COUNT_STATS
     if events is not None:
         o.ev_kernel_start = events[0].cuda_event
         o.ev_kernel_stop = events[1].cuda_event
@@ -144,8 +142,8 @@ class Counter:
     """
 
     def __init__(self, graph: Graph, plans, chunk=0, split=0, cap=0, waves_per_cu=0,
-                 roots=None, cancel=None, stats: bool = False, kernel_events: bool = False,
-                 stream=None):
+                 roots=None, cancel=None, kernel_events: bool = False, stream=None,
+                 merge_min=0, merge_ratio=0, split_work=0):
         import torch
         self.graph = graph
         self.plans = list(plans)
@@ -154,7 +152,6 @@ class Counter:
         if roots is not None:
             self.roots = _u32_tensor(np.asarray(roots, dtype=np.uint32), dev)
         self.cancel = cancel
-        self.stats = torch.zeros(4 * len(self.plans), dtype=torch.int64, device=dev) if stats else None
         self.events = None
         if kernel_events:
             # events around the count kernel itself; recording once creates them
@@ -163,8 +160,8 @@ class Counter:
                 self.events = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                 for ev in self.events:
                     ev.record(s)
-        self.opts = make_opts(chunk, split, cap, waves_per_cu, self.roots, cancel, self.stats,
-                              self.events)
+        self.opts = make_opts(chunk, split, cap, waves_per_cu, self.roots, cancel, self.events,
+                              merge_min, merge_ratio, split_work)
         self._parr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
         ws = lib().xm_workspace_size(graph.handle, len(self.plans), self._parr, ctypes.byref(self.opts))
         if ws == 0:
@@ -209,11 +206,6 @@ class Counter:
         """Duration of the last count kernel (call after the stream completed)."""
         return self.events[0].elapsed_time(self.events[1])
 
-    def stats_list(self):
-        s = self.stats.cpu().numpy().view(np.uint64).reshape(-1, 4)
-        return [dict(elements=int(r[0]), fetches=int(r[1]), partial_matches=int(r[2]),
-                     root_tasks=int(r[3])) for r in s]
-
     def close(self):
         if self.exec is not None:
             lib().xm_free_exec(self.exec)
@@ -224,6 +216,22 @@ class Counter:
             self.close()
         except Exception:
             pass
+
+
+def plan_work(digraph, plan: Plan, roots=None, threads: int = 1) -> dict:
+    """Algorithmic work of a plan on a host graph (statistics only, no count)."""
+    arrs = [np.ascontiguousarray(a, dtype=np.uint32) for a in
+            (digraph.out_off, digraph.out_adj, digraph.in_off, digraph.in_adj)]
+    arrs = [a if a.size else np.zeros(1, dtype=np.uint32) for a in arrs]
+    out = (ctypes.c_uint64 * 4)()
+    r, nr = None, 0
+    if roots is not None:
+        r = np.ascontiguousarray(roots, dtype=np.uint32)
+        nr = int(r.size)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    check(lib().xm_plan_work(int(digraph.n), *[ptr(a) for a in arrs], plan.handle,
+                             ptr(r) if r is not None else None, nr, threads, out))
+    return dict(elements=out[0], fetches=out[1], partial_matches=out[2], roots=out[3])
 
 
 def count(graph: Graph, plans, stream=None, **opts):

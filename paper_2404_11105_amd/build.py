@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libxminer.so")
 ARCH = os.environ.get("XM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["planner.cpp", "runtime.cpp", "count.hip"]
+SOURCES = ["planner.cpp", "runtime.cpp", "work.cpp", "count.hip"]
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Wall", "-Wno-unused-function",

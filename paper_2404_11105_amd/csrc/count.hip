@@ -103,6 +103,7 @@ struct Lds {
     uint32_t* chk_len;   // [maxc][64]
     uint32_t* hist;      // [64][16]
     uint32_t* st;        // wave state: cur[8], pofs[8], n[8]
+    uint32_t* mbuf;      // [kMergeChunk]: probe-list chunk of the cooperative merge
 };
 
 __device__ __forceinline__ Lds carve(uint32_t* w, uint32_t maxc) {
@@ -119,6 +120,8 @@ __device__ __forceinline__ Lds carve(uint32_t* w, uint32_t maxc) {
     s.chk_off = q;
     s.chk_len = q + maxc * 64;
     q += 2 * maxc * 64;
+    s.mbuf = q;
+    q += kMergeChunk;
     s.st = q;
     s.hist = q + 32;
     return s;
@@ -145,7 +148,6 @@ struct Ctx {
     uint32_t* scr;
     uint32_t lane;
     unsigned long long acc_lo, acc_hi;  // per-lane 128-bit partial (leaf groups)
-    unsigned long long st_elems, st_fetch, st_pm;
 };
 
 // First-level base list length of root r for plan P (shortest constraint list).
@@ -297,7 +299,6 @@ __device__ __forceinline__ bool member_sig(const Ctx& C, const LevelDesc& S, uin
 
 // Expand one window of level lv from the parents in level lv-1.  Returns the
 // number of children written to level lv's buffer.
-template <bool STATS>
 __device__ uint32_t expand(Ctx& C, uint32_t lv) {
     const KArgs& a = *C.a;
     const LevelDesc& D = C.P->lvl[lv];
@@ -310,17 +311,6 @@ __device__ uint32_t expand(Ctx& C, uint32_t lv) {
     const bool pv = p < nparents;
     uint32_t len = phase_a<false>(C, D, lv, p, pv, true);
     if (pv && lane == 0) len -= pofs;
-    if (STATS && pv) {
-        C.st_elems += len;
-        C.st_fetch += 1;
-        for (uint32_t c = 0; c < D.n_cons; c++) {
-            uint32_t l = C.s.chk_len[c * 64 + lane];
-            if (l != kSkip) {
-                C.st_elems += l;
-                C.st_fetch += 1;
-            }
-        }
-    }
     uint32_t incl = scan_incl(len, lane);
     C.s.incl[lane] = incl;
     const bool seg = (C.P->seg_src >> lv) & 1u;
@@ -361,7 +351,6 @@ __device__ uint32_t expand(Ctx& C, uint32_t lv) {
         }
         nout += (uint32_t)__popcll(m);
     }
-    if (STATS && lane == 0) C.st_pm += nout;
     wave_sync();
     if (seg) {
         // children of each parent are contiguous in output order
@@ -393,14 +382,63 @@ __device__ uint32_t expand(Ctx& C, uint32_t lv) {
     return nout;
 }
 
+// |A intersect B| minus the listed bound nodes, for one partial match, by the
+// whole wave: both sorted lists are walked in chunks of kMergeChunk elements
+// (A in registers, B staged in LDS); each A element is looked up in the B
+// chunk, and the chunk with the smaller maximum advances (both on a tie), so
+// every matching pair is seen exactly once.  Reads are coalesced and no
+// dependent global search is needed (merge path for balanced list sizes).
+__device__ uint32_t merge_count(const Lds& s, const uint32_t* __restrict__ A, uint32_t na,
+                                const uint32_t* __restrict__ B, uint32_t nb, const uint32_t* excl,
+                                uint32_t n_excl, uint32_t lane) {
+    constexpr uint32_t U = kMergeChunk / 64;
+    uint32_t ia = 0, ib = 0, cnt = 0;
+    while (ia < na && ib < nb) {
+        uint32_t av[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++) {
+            uint32_t i = ia + u * 64 + lane;
+            av[u] = i < na ? A[i] : 0xFFFFFFFFu;
+            uint32_t k = ib + u * 64 + lane;
+            s.mbuf[u * 64 + lane] = k < nb ? B[k] : 0xFFFFFFFFu;
+        }
+        const uint32_t alast = (ia + kMergeChunk < na ? ia + kMergeChunk : na) - 1;
+        const uint32_t blast = (ib + kMergeChunk < nb ? ib + kMergeChunk : nb) - 1;
+        const uint32_t amax = A[alast], bmax = B[blast];
+        const uint32_t nbc = blast - ib + 1;
+        wave_sync();
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++) {
+            uint32_t x = av[u];
+            if (ia + u * 64 + lane < na) {
+                uint32_t base = 0, n = nbc;
+                while (n > 1) {
+                    uint32_t h = n >> 1;
+                    base = (s.mbuf[base + h] <= x) ? base + h : base;
+                    n -= h;
+                }
+                bool ok = s.mbuf[base] == x;
+                for (uint32_t t = 0; t < n_excl; t++) ok = ok && (x != excl[t]);
+                cnt += ok ? 1u : 0u;
+            }
+        }
+        if (amax <= bmax) ia += kMergeChunk;
+        if (bmax <= amax) ib += kMergeChunk;
+        wave_sync();
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) cnt += __shfl_xor(cnt, d, 64);
+    return cnt;
+}
+
 // Count the leaf group for every partial match in level `lv` (= e - 1).
-template <bool STATS>
+template <bool NONLIN>
 __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
     const KArgs& a = *C.a;
     const PlanDesc* P = C.P;
     const uint32_t lane = C.lane;
     const uint32_t nsig = P->n_sig;
-    const bool linear = P->linear != 0;
+    const bool linear = !NONLIN || P->linear != 0;
     const uint32_t nb = lv + 1;  // bound levels 0..lv
     for (uint32_t w0 = 0; w0 < nprefix; w0 += 64) {
         const uint32_t p = w0 + lane;
@@ -419,21 +457,50 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
             for (int q = 0; q < 16; q++) C.s.hist[lane * 16 + q] = 0;
         }
         unsigned long long lin = 0;
+        if (linear && P->sig[0].n_cons == 1 && P->sig[0].reuse == kNoReuse) {
+            // one leaf drawn from one list L: |L| minus the bound nodes found in L
+            const LevelDesc& S = P->sig[0];
+            uint32_t v = 0;
+            if (pv) {
+                const DevGraph& g = a.g;
+                uint32_t nd = C.s.bound[S.cons_lvl[0] * 64 + lane];
+                const uint32_t* off = off_of(g, S.cons_dir[0]);
+                uint32_t o = off[nd];
+                uint32_t l = off[nd + 1] - o;
+                const uint32_t* L = adj_of(g, S.cons_dir[0]) + o;
+                v = l;
+                for (uint32_t b = 0; b < nb; b++)
+                    if (((S.inj >> b) & 1u) && contains(L, l, C.s.bound[b * 64 + lane])) v -= 1;
+            }
+            unsigned long long o = C.acc_lo;
+            C.acc_lo += v;
+            if (C.acc_lo < o) C.acc_hi += 1;
+            wave_sync();
+            continue;
+        }
         for (uint32_t s = 0; s < nsig; s++) {
             if (!P->sig_scan[s]) continue;
             const LevelDesc& S = P->sig[s];
             uint32_t len = phase_a<true>(C, S, nb, p, pv, false);
-            if (STATS && pv) {
-                C.st_elems += len;
-                C.st_fetch += 1;
-                for (uint32_t c = 0; c < S.n_cons; c++) {
-                    uint32_t l = C.s.chk_len[c * 64 + lane];
-                    if (l != kSkip) {
-                        C.st_elems += l;
-                        C.st_fetch += 1;
+            // one leaf whose set is a base list and one probe list: balanced big
+            // pairs leave the flattened pass for the cooperative merge
+            uint32_t probe_c = kSkip;
+            bool big = false;
+            if (linear && pv) {
+                uint32_t nprobe = 0;
+                for (uint32_t c = 0; c < S.n_cons; c++)
+                    if (C.s.chk_len[c * 64 + lane] != kSkip) {
+                        probe_c = c;
+                        nprobe++;
                     }
+                if (nprobe == 1) {
+                    uint32_t pl = C.s.chk_len[probe_c * 64 + lane];
+                    uint32_t mn = len < pl ? len : pl, mx = len < pl ? pl : len;
+                    big = mn >= a.merge_min && (uint64_t)mx <= (uint64_t)a.merge_ratio * mn;
                 }
             }
+            uint64_t bigmask = __ballot(big);
+            if (big) len = 0;
             uint32_t incl = scan_incl(len, lane);
             C.s.incl[lane] = incl;
             const uint32_t T = uni(__shfl(incl, 63, 64));
@@ -462,6 +529,28 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
                 }
             }
             wave_sync();
+            // balanced big pairs, one partial match at a time
+            while (bigmask) {
+                const uint32_t j = (uint32_t)__builtin_ctzll(bigmask);
+                bigmask &= bigmask - 1;
+                const uint32_t kind = uni(C.s.base_kind[j]);
+                const uint32_t boff = uni(C.s.base_off[j]);
+                const uint32_t blen = uni(C.s.base_len[j]);
+                uint32_t pc = 0;
+                for (uint32_t c = 0; c < S.n_cons; c++)
+                    if (C.s.chk_len[c * 64 + j] != kSkip) pc = c;
+                pc = uni(pc);
+                const uint32_t poff = uni(C.s.chk_off[pc * 64 + j]);
+                const uint32_t plen = uni(C.s.chk_len[pc * 64 + j]);
+                const uint32_t* A = (kind == 2) ? lvl_arrays(C.scr, a.cap, S.reuse).node + boff
+                                                : adj_of(a.g, kind) + boff;
+                const uint32_t* B = adj_of(a.g, S.cons_dir[pc]) + poff;
+                uint32_t ex[kMaxK];
+                uint32_t nex = 0;
+                for (uint32_t b = 0; b < nb; b++)
+                    if ((S.inj >> b) & 1u) ex[nex++] = uni(C.s.bound[b * 64 + j]);
+                lin += merge_count(C.s, A, blen, B, plen, ex, nex, lane);
+            }
         }
         if (linear) {
             if (lane == 0) {
@@ -470,20 +559,17 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
                 if (C.acc_lo < o) C.acc_hi += 1;
             }
         } else if (pv) {
+            // superset sums in place: h[m] becomes |intersection of the sets in m|
+            uint32_t* h = C.s.hist + lane * 16;
+            for (uint32_t b = 0; b < nsig; b++)
+                for (uint32_t m = 0; m < 16; m++)
+                    if (!((m >> b) & 1u)) h[m] += h[m | (1u << b)];
             // inclusion-exclusion over set partitions of the leaves
-            uint32_t full = (1u << nsig) - 1u;
-            uint64_t I[16];
-            for (uint32_t m = 1; m <= full; m++) {
-                uint64_t sum = 0;
-                for (uint32_t m2 = m; m2 <= full; m2++)
-                    if ((m2 & m) == m) sum += C.s.hist[lane * 16 + m2];
-                I[m] = sum;
-            }
             __int128 val = 0;
             for (uint32_t t = 0; t < P->n_terms; t++) {
                 const Term& tm = P->terms[t];
                 __int128 prod = tm.coef;
-                for (uint32_t b = 0; b < tm.nb; b++) prod *= (__int128)I[tm.mask[b]];
+                for (uint32_t b = 0; b < tm.nb; b++) prod *= (__int128)h[tm.mask[b]];
                 val += prod;
             }
             unsigned __int128 v = (unsigned __int128)val;
@@ -496,7 +582,6 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
     }
 }
 
-template <bool STATS>
 __device__ void flush(Ctx& C) {
     unsigned long long lo = C.acc_lo, hi = C.acc_hi;
     // wave reduction of 128-bit partials
@@ -511,31 +596,15 @@ __device__ void flush(Ctx& C) {
     if (C.lane == 0 && (lo | hi))
         add_u128(C.a->counts + 2 * C.pi, lo, hi, C.a->plan_flags + C.pi);
     C.acc_lo = C.acc_hi = 0;
-    if (STATS) {
-        unsigned long long e = C.st_elems, f = C.st_fetch, m = C.st_pm;
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) {
-            e += __shfl_xor(e, d, 64);
-            f += __shfl_xor(f, d, 64);
-            m += __shfl_xor(m, d, 64);
-        }
-        if (C.lane == 0) {
-            unsigned long long* sp = C.a->stats + 4 * C.pi;
-            if (e) atomicAdd(sp + 0, e);
-            if (f) atomicAdd(sp + 1, f);
-            if (m) atomicAdd(sp + 2, m);
-        }
-        C.st_elems = C.st_fetch = C.st_pm = 0;
-    }
 }
 
 // Depth-first exploration of the roots held in level 0.
-template <bool STATS>
+template <bool NONLIN>
 __device__ void explore(Ctx& C, uint32_t n0) {
     const uint32_t e = C.P->e;
     uint32_t* st = C.s.st;
     if (e == 1) {
-        count_leaves<STATS>(C, 0, n0);
+        count_leaves<NONLIN>(C, 0, n0);
         return;
     }
     if (C.lane == 0) {
@@ -553,9 +622,9 @@ __device__ void explore(Ctx& C, uint32_t n0) {
             lv -= 1;
             continue;
         }
-        uint32_t nout = expand<STATS>(C, lv);
+        uint32_t nout = expand(C, lv);
         if (lv == e - 1) {
-            if (nout) count_leaves<STATS>(C, lv, nout);
+            if (nout) count_leaves<NONLIN>(C, lv, nout);
         } else if (nout) {
             lv += 1;
             if (C.lane == 0) {
@@ -567,7 +636,7 @@ __device__ void explore(Ctx& C, uint32_t n0) {
     }
 }
 
-template <bool STATS>
+template <bool NONLIN>
 __global__ void __launch_bounds__(kBlockThreads) count_kernel(KArgs a) {
     extern __shared__ uint32_t smem[];
     Ctx C;
@@ -578,7 +647,6 @@ __global__ void __launch_bounds__(kBlockThreads) count_kernel(KArgs a) {
     const uint64_t gw = (uint64_t)blockIdx.x * kWavesPerBlock + wid;
     C.scr = a.scratch + gw * (uint64_t)a.wave_words;
     C.acc_lo = C.acc_hi = 0;
-    C.st_elems = C.st_fetch = C.st_pm = 0;
     const uint32_t split_count = uni(__atomic_load_n(&a.ctl[kCtlSplitCount], __ATOMIC_RELAXED));
     const uint32_t n_split = split_count < a.split_cap ? split_count : a.split_cap;
     const uint32_t chunks_per_plan = (a.n_src + a.chunk - 1) / a.chunk;
@@ -641,7 +709,8 @@ __global__ void __launch_bounds__(kBlockThreads) count_kernel(KArgs a) {
             }
             if (ok && C.P->e >= 2) {
                 uint32_t l = level1_len(a.g, C.P, r);
-                ok = l > 0 && l <= a.split;  // longer lists were queued by the split kernel
+                // longer lists were queued as sub-ranges by the split kernel
+                ok = l > 0 && l <= item_size(l, a.split, a.split_work);
             }
             uint64_t m = __ballot(ok);
             if (ok) {
@@ -653,9 +722,8 @@ __global__ void __launch_bounds__(kBlockThreads) count_kernel(KArgs a) {
             n0 = (uint32_t)__popcll(m);
         }
         wave_sync();
-        if (STATS && C.lane == 0) atomicAdd(a.stats + 4 * C.pi + 3, (unsigned long long)n0);
-        if (n0) explore<STATS>(C, n0);
-        flush<STATS>(C);
+        if (n0) explore<NONLIN>(C, n0);
+        flush(C);
     }
 }
 
@@ -675,16 +743,17 @@ __global__ void split_kernel(KArgs a) {
         uint2 d = a.g.deg[r];
         if (d.x < P->root_dout || d.y < P->root_din) continue;
         uint32_t len = level1_len(a.g, P, r);
-        if (len <= a.split) continue;
-        uint32_t nit = (len + a.split - 1) / a.split;
+        const uint32_t sz = item_size(len, a.split, a.split_work);
+        if (len <= sz) continue;
+        uint32_t nit = (len + sz - 1) / sz;
         uint32_t base = atomicAdd(&a.ctl[kCtlSplitCount], nit);
         if (base + nit > a.split_cap) {
             atomicOr(&a.ctl[kCtlQueueFull], 1u);
             continue;
         }
         for (uint32_t q = 0; q < nit; q++) {
-            uint32_t lo = q * a.split;
-            uint32_t hi = lo + a.split < len ? lo + a.split : len;
+            uint32_t lo = q * sz;
+            uint32_t hi = lo + sz < len ? lo + sz : len;
             a.split_items[base + q] = make_uint4(pi, r, lo, hi);
         }
     }
@@ -704,8 +773,6 @@ __global__ void init_kernel(InitArgs a) {
         for (uint32_t i = tid; i < kCtlWords; i += nthr) a.ctl[i] = 0;
         for (uint32_t i = tid; i < a.n_plans; i += nthr) a.plan_flags[i] = 0;
         for (uint32_t i = tid; i < 2 * a.n_plans; i += nthr) a.counts[i] = 0;
-        if (a.stats)
-            for (uint32_t i = tid; i < 4 * a.n_plans; i += nthr) a.stats[i] = 0;
     }
 }
 
@@ -720,8 +787,18 @@ __global__ void finalize_kernel(KArgs a) {
     }
 }
 
+int count_blocks_per_cu(bool nonlin, size_t lds_bytes) {
+    int nb = 0;
+    hipError_t e;
+    if (nonlin)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, count_kernel<true>, kBlockThreads, lds_bytes);
+    else
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, count_kernel<false>, kBlockThreads, lds_bytes);
+    return e == hipSuccess ? nb : 0;
+}
+
 hipError_t launch_count(const InitArgs* inits, int n_inits, const KArgs& a, uint32_t n_blocks,
-                        bool stats, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_stop) {
+                        hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_stop) {
     for (int i = 0; i < n_inits; i++) {
         hipLaunchKernelGGL(init_kernel, dim3(64), dim3(256), 0, stream, inits[i]);
     }
@@ -735,7 +812,7 @@ hipError_t launch_count(const InitArgs* inits, int n_inits, const KArgs& a, uint
         hipError_t e = hipEventRecord(ev_start, stream);
         if (e != hipSuccess) return e;
     }
-    if (stats)
+    if (a.nonlinear)
         hipLaunchKernelGGL(count_kernel<true>, dim3(n_blocks), dim3(kBlockThreads), lds, stream, a);
     else
         hipLaunchKernelGGL(count_kernel<false>, dim3(n_blocks), dim3(kBlockThreads), lds, stream, a);

@@ -12,6 +12,9 @@ constexpr int kBlockThreads = 64 * kWavesPerBlock;
 constexpr uint32_t kHubMin = 64;    // nodes with a list longer than this are hub candidates
 constexpr int kMaxPlansPerInit = 240;
 constexpr int kLvlArrays = 5;       // node, parent, seg_begin, seg_count, aux per level
+constexpr uint32_t kMergeChunk = 256; // elements per list chunk in the cooperative merge
+constexpr uint32_t kMergeMin = 0xFFFFFFFFu;  // default: merge off (see xm_count_opts.merge_min)
+constexpr uint32_t kMergeRatio = 16;  // ... and within this length ratio -> merge
 
 // Control words at the start of the workspace.
 enum Ctl : uint32_t {
@@ -38,7 +41,8 @@ struct KArgs {
     const PlanDesc* plans;      // table in the workspace
     uint32_t n_plans;
     uint32_t chunk;             // roots per root work item (<= 64)
-    uint32_t split;             // first-level lists longer than this are split
+    uint32_t split;             // largest first-level sub-range of a split root
+    uint32_t split_work;        // target (sub-range length x first-level length) per task
     uint32_t cap;               // entries per level buffer
     uint32_t* ctl;              // control words
     uint32_t* plan_flags;       // per plan: bit 0 overflow
@@ -50,12 +54,14 @@ struct KArgs {
     uint32_t n_hubs;
     uint32_t lds_words;         // LDS words per wave
     uint32_t maxc;              // largest constraint count over plans and signatures
+    uint32_t nonlinear;         // some plan counts a leaf group of several vertices
+    uint32_t merge_min;         // cooperative merge thresholds
+    uint32_t merge_ratio;
     uint32_t wave_words;        // scratch words per wave
     uint32_t* scratch;          // n_waves * wave_words
     unsigned long long* counts; // 2 per plan
     int32_t* status;            // 1 per plan
     const int32_t* cancel;      // nullable
-    unsigned long long* stats;  // nullable: 4 per plan
 };
 
 struct InitArgs {
@@ -63,23 +69,46 @@ struct InitArgs {
     const PlanDesc* src[kMaxPlansPerInit];
     uint32_t first, count;      // plans [first, first+count) of the table
     uint32_t n_plans;
-    uint32_t zero_ctl;          // 1: also clear control words, flags, counts, stats
+    uint32_t zero_ctl;          // 1: also clear control words, flags and counts
     uint32_t* ctl;
     uint32_t* plan_flags;
     unsigned long long* counts;
-    unsigned long long* stats;
 };
+
+// First-level sub-range length for a root whose first-level list has L1
+// entries: the task size shrinks as the list grows, because each first-level
+// candidate of a long list usually carries a long list below it.
+__host__ __device__ inline uint32_t item_size(uint32_t L1, uint32_t split, uint32_t split_work) {
+    uint32_t s = L1 ? split_work / L1 : split;
+    s = s < split ? s : split;
+    return s < 1 ? 1 : s;
+}
 
 // LDS words per wave for a given largest constraint count and leaf mode.
 inline uint32_t lds_words_for(uint32_t maxc, bool nonlinear) {
     return 2 * kMaxK * 64      // bound values, ancestor indices
            + 6 * 64            // base offset/length/kind, inclusive scan, segment counts, spare
            + 2 * maxc * 64     // check-list offset/length per constraint
+           + kMergeChunk       // merge chunk
            + (nonlinear ? 16 * 64 : 0)  // leaf-group histograms
            + 32;               // wave state
 }
 
+// Resident 256-thread blocks per compute unit for the count kernel variant.
+int count_blocks_per_cu(bool nonlin, size_t lds_bytes);
+
 hipError_t launch_count(const InitArgs* inits, int n_inits, const KArgs& a, uint32_t n_blocks,
-                        bool stats, hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_stop);
+                        hipStream_t stream, hipEvent_t ev_start, hipEvent_t ev_stop);
+
+// Host-side algorithmic work of a plan (work.cpp).
+struct HostCsr {
+    const uint32_t *out_off, *out_adj, *in_off, *in_adj;
+    uint32_t n;
+};
+struct WorkOut {
+    uint64_t elements = 0, fetches = 0, partial = 0, roots = 0;
+};
+void plan_work(const HostCsr& g, const PlanDesc& p, const uint32_t* roots, uint32_t n_roots,
+               unsigned threads, WorkOut& out);
 
 }  // namespace xm

@@ -82,7 +82,7 @@ int plan_device_desc(xm_plan_t* p, int dev, const PlanDesc** out) {
 }
 
 struct Layout {
-    uint32_t chunk, split, cap, waves_per_cu, n_waves, n_blocks, e_max, maxc;
+    uint32_t chunk, split, split_work, cap, waves_per_cu, n_waves, n_blocks, e_max, maxc;
     bool nonlinear;
     size_t off_ctl, off_flags, off_table, off_split, off_scratch, total;
     uint32_t split_cap, wave_words, lds_words;
@@ -96,15 +96,17 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
     if (n_plans == 0 || !plans) return fail(XM_ERR_INVALID, "no plans");
     if (o && o->struct_size != 0 && o->struct_size < sizeof(xm_count_opts))
         return fail(XM_ERR_INVALID, "xm_count_opts.struct_size too small");
-    L.chunk = (o && o->chunk) ? o->chunk : 8;
-    L.split = (o && o->split) ? o->split : 512;
+    L.chunk = (o && o->chunk) ? o->chunk : 4;
+    L.split = (o && o->split) ? o->split : 64;
+    L.split_work = (o && o->split_work) ? o->split_work : 8192;
     L.cap = (o && o->cap) ? o->cap : 4096;
-    L.waves_per_cu = (o && o->waves_per_cu) ? o->waves_per_cu : 16;
+    L.waves_per_cu = (o && o->waves_per_cu) ? o->waves_per_cu : 0;  // 0: from occupancy
     if (L.chunk > 64) return fail(XM_ERR_INVALID, "chunk must be <= 64");
     if (L.split < xm::kHubMin) return fail(XM_ERR_INVALID, "split must be >= 64");
+    if (L.split_work < xm::kHubMin * xm::kHubMin) return fail(XM_ERR_INVALID, "split_work must be >= 4096");
     if (L.cap < L.split || L.cap < 64) return fail(XM_ERR_INVALID, "cap must be >= split and >= 64");
     if (L.cap > (1u << 24)) return fail(XM_ERR_INVALID, "cap too large");
-    if (L.waves_per_cu < 4 || L.waves_per_cu > 32)
+    if (L.waves_per_cu != 0 && (L.waves_per_cu < 4 || L.waves_per_cu > 32))
         return fail(XM_ERR_INVALID, "waves_per_cu must be in 4..32");
     uint32_t max_list = std::max(g->max_out, g->max_in);
     if ((uint64_t)max_list * 64 >= (1ull << 32))
@@ -122,6 +124,12 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
         if (!D.linear) L.nonlinear = true;
         if (D.e >= 2) splittable++;
     }
+    L.lds_words = xm::lds_words_for(L.maxc, L.nonlinear);
+    if (L.waves_per_cu == 0) {
+        // as many waves as can be resident at once: the kernel is persistent
+        int bpc = xm::count_blocks_per_cu(L.nonlinear, (size_t)L.lds_words * 4 * xm::kWavesPerBlock);
+        L.waves_per_cu = (uint32_t)std::max(1, std::min(bpc, 8)) * xm::kWavesPerBlock;
+    }
     L.n_waves = (uint32_t)g->n_cu * L.waves_per_cu;
     L.n_waves = (L.n_waves + xm::kWavesPerBlock - 1) / xm::kWavesPerBlock * xm::kWavesPerBlock;
     L.n_blocks = L.n_waves / xm::kWavesPerBlock;
@@ -130,10 +138,15 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
         return fail(XM_ERR_INVALID, "plans need more LDS than a workgroup may use");
     // split queue capacity: every splittable plan may split every hub root
     uint64_t items = 0;
+    // pieces per root grow with the list length, so a hub's longest list bounds them
+    auto pieces = [&](uint32_t len) -> uint64_t {
+        uint32_t sz = xm::item_size(len, L.split, L.split_work);
+        return len > sz ? (len + sz - 1) / sz : 0;
+    };
     if (o && o->roots_dev) {
-        items = (uint64_t)o->n_roots * ((max_list + L.split - 1) / L.split);
+        items = (uint64_t)o->n_roots * pieces(max_list);
     } else {
-        for (uint32_t h : g->hub_len) items += (h + L.split - 1) / L.split;
+        for (uint32_t h : g->hub_len) items += pieces(h);
     }
     items *= splittable;
     if (items > 0xFFFFFFF0ull) return fail(XM_ERR_INVALID, "split queue too large; raise split");
@@ -162,8 +175,7 @@ int enqueue_count(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const*
     if (rc) return rc;
     if (!ws || ws_bytes < L.total) return fail(XM_ERR_WORKSPACE, "workspace missing or too small");
     if (!counts || !status) return fail(XM_ERR_INVALID, "counts/status buffers are NULL");
-    if (o && (o->flags & XM_COUNT_STATS) && !o->stats_dev)
-        return fail(XM_ERR_INVALID, "XM_COUNT_STATS needs stats_dev");
+    if (o && o->flags != 0) return fail(XM_ERR_INVALID, "unknown xm_count_opts flag");
     if (o && o->roots_dev && o->n_roots == 0) return fail(XM_ERR_INVALID, "empty root subset");
     int cur_dev = 0;
     HIP_TRY(hipGetDevice(&cur_dev), "hipGetDevice");
@@ -176,6 +188,7 @@ int enqueue_count(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const*
     a.n_plans = n_plans;
     a.chunk = L.chunk;
     a.split = L.split;
+    a.split_work = L.split_work;
     a.cap = L.cap;
     a.ctl = reinterpret_cast<uint32_t*>(base + L.off_ctl);
     a.plan_flags = reinterpret_cast<uint32_t*>(base + L.off_flags);
@@ -187,13 +200,14 @@ int enqueue_count(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const*
     a.n_hubs = g->n_hubs;
     a.lds_words = L.lds_words;
     a.maxc = L.maxc;
+    a.merge_min = (o && o->merge_min) ? o->merge_min : xm::kMergeMin;
+    a.merge_ratio = (o && o->merge_ratio) ? o->merge_ratio : xm::kMergeRatio;
+    a.nonlinear = L.nonlinear ? 1u : 0u;
     a.wave_words = L.wave_words;
     a.scratch = reinterpret_cast<uint32_t*>(base + L.off_scratch);
     a.counts = reinterpret_cast<unsigned long long*>(counts);
     a.status = status;
     a.cancel = o ? o->cancel_dev : nullptr;
-    bool stats = o && (o->flags & XM_COUNT_STATS);
-    a.stats = stats ? reinterpret_cast<unsigned long long*>(o->stats_dev) : nullptr;
 
     std::vector<xm::InitArgs> inits;
     for (uint32_t first = 0; first < n_plans; first += xm::kMaxPlansPerInit) {
@@ -213,12 +227,11 @@ int enqueue_count(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const*
         ia.ctl = a.ctl;
         ia.plan_flags = a.plan_flags;
         ia.counts = a.counts;
-        ia.stats = a.stats;
         inits.push_back(ia);
     }
     hipEvent_t ev0 = o ? static_cast<hipEvent_t>(o->ev_kernel_start) : nullptr;
     hipEvent_t ev1 = o ? static_cast<hipEvent_t>(o->ev_kernel_stop) : nullptr;
-    hipError_t e = xm::launch_count(inits.data(), (int)inits.size(), a, L.n_blocks, stats, stream, ev0, ev1);
+    hipError_t e = xm::launch_count(inits.data(), (int)inits.size(), a, L.n_blocks, stream, ev0, ev1);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return XM_OK;
 }
@@ -407,6 +420,22 @@ int xm_load_graph(uint32_t n, uint32_t m, const uint32_t* out_off, const uint32_
         return hip_fail(e, "upload degrees");
     }
     *out = g;
+    return XM_OK;
+}
+
+int xm_plan_work(uint32_t n, const uint32_t* out_off, const uint32_t* out_adj, const uint32_t* in_off,
+                 const uint32_t* in_adj, const xm_plan_t* p, const uint32_t* roots, uint32_t n_roots,
+                 uint32_t threads, uint64_t out[4]) {
+    if (!p || !out || !out_off || !in_off || n == 0) return fail(XM_ERR_INVALID, "NULL argument");
+    if ((out_off[n] > 0 && !out_adj) || (in_off[n] > 0 && !in_adj))
+        return fail(XM_ERR_INVALID, "NULL adjacency array");
+    xm::HostCsr h{out_off, out_adj, in_off, in_adj, n};
+    xm::WorkOut w;
+    xm::plan_work(h, p->desc, roots, n_roots, threads ? threads : 1, w);
+    out[0] = w.elements;
+    out[1] = w.fetches;
+    out[2] = w.partial;
+    out[3] = w.roots;
     return XM_OK;
 }
 

@@ -1,0 +1,187 @@
+// work.cpp — algorithmic work of a plan on a graph, measured on the host.
+//
+// Walks the plan's partial matches level by level exactly as the plan
+// defines them (the candidate sets of the enumerated levels are built; leaf
+// groups only contribute the lengths of the lists they read) and sums, per
+// partial match and level, the length of the base list plus the lengths of
+// the lists probed for membership.  This is the algorithmic element count of
+// the plan, independent of how a launch is tuned (hub splits, window sizes).
+// It is a statistic for roofline accounting: it returns no embedding count.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "kernels.h"
+
+namespace xm {
+
+namespace {
+
+struct Walker {
+    const HostCsr& G;
+    const PlanDesc& P;
+    WorkOut w;
+    uint32_t phi[kMaxK];
+    std::vector<uint32_t> cand[kMaxK];
+
+    Walker(const HostCsr& g, const PlanDesc& p) : G(g), P(p) {}
+
+    void list(uint32_t node, uint32_t dir, const uint32_t*& a, uint32_t& len) const {
+        const uint32_t* off = dir ? G.in_off : G.out_off;
+        a = (dir ? G.in_adj : G.out_adj) + off[node];
+        len = off[node + 1] - off[node];
+    }
+
+    static bool has(const uint32_t* a, uint32_t len, uint32_t x) {
+        return std::binary_search(a, a + len, x);
+    }
+
+    // Base and probe lists of level desc D at depth lv (levels < lv bound).
+    void lists(const LevelDesc& D, bool& from_level, const uint32_t*& base, uint32_t& blen,
+               const uint32_t* probe[kMaxCons], uint32_t plen[kMaxCons], int& np) {
+        np = 0;
+        from_level = D.reuse != kNoReuse;
+        if (from_level) {
+            base = cand[D.reuse].data();
+            blen = (uint32_t)cand[D.reuse].size();
+            for (int c = 0; c < D.n_cons; c++)
+                if ((D.extra >> c) & 1u) {
+                    list(phi[D.cons_lvl[c]], D.cons_dir[c], probe[np], plen[np]);
+                    np++;
+                }
+            return;
+        }
+        int bc = 0;
+        const uint32_t* a[kMaxCons];
+        uint32_t l[kMaxCons];
+        for (int c = 0; c < D.n_cons; c++) {
+            list(phi[D.cons_lvl[c]], D.cons_dir[c], a[c], l[c]);
+            if (l[c] < l[bc]) bc = c;
+        }
+        base = a[bc];
+        blen = l[bc];
+        for (int c = 0; c < D.n_cons; c++)
+            if (c != bc) {
+                probe[np] = a[c];
+                plen[np++] = l[c];
+            }
+    }
+
+    void leaves(uint32_t nb) {
+        const LevelDesc& S0 = P.sig[0];
+        if (P.linear && S0.n_cons == 1 && S0.reuse == kNoReuse) {
+            const uint32_t* a;
+            uint32_t l;
+            list(phi[S0.cons_lvl[0]], S0.cons_dir[0], a, l);
+            w.elements += l;
+            w.fetches += 1;
+            return;
+        }
+        (void)nb;
+        for (uint32_t s = 0; s < P.n_sig; s++) {
+            if (!P.sig_scan[s]) continue;
+            bool fl;
+            const uint32_t* base;
+            uint32_t blen;
+            const uint32_t* probe[kMaxCons];
+            uint32_t plen[kMaxCons];
+            int np;
+            lists(P.sig[s], fl, base, blen, probe, plen, np);
+            w.elements += blen;
+            w.fetches += 1;
+            for (int i = 0; i < np; i++) {
+                w.elements += plen[i];
+                w.fetches += 1;
+            }
+        }
+    }
+
+    void level(uint32_t lv) {
+        if (lv == P.e) {
+            leaves(lv);
+            return;
+        }
+        const LevelDesc& D = P.lvl[lv];
+        bool fl;
+        const uint32_t* base;
+        uint32_t blen;
+        const uint32_t* probe[kMaxCons];
+        uint32_t plen[kMaxCons];
+        int np;
+        lists(D, fl, base, blen, probe, plen, np);
+        w.elements += blen;
+        w.fetches += 1;
+        for (int i = 0; i < np; i++) {
+            w.elements += plen[i];
+            w.fetches += 1;
+        }
+        std::vector<uint32_t>& out = cand[lv];
+        out.clear();
+        for (uint32_t i = 0; i < blen; i++) {
+            uint32_t x = base[i];
+            bool ok = true;
+            for (uint32_t j = 0; j < lv && ok; j++)
+                if (((D.inj >> j) & 1u) && x == phi[j]) ok = false;
+            if (ok && D.deg_check) {
+                uint32_t dout = G.out_off[x + 1] - G.out_off[x], din = G.in_off[x + 1] - G.in_off[x];
+                ok = dout >= D.dmin_out && din >= D.dmin_in;
+            }
+            for (int c = 0; c < np && ok; c++) ok = has(probe[c], plen[c], x);
+            if (ok) out.push_back(x);
+        }
+        w.partial += out.size();
+        // deeper levels only write cand[> lv], so cand[lv] stays valid for reuse
+        for (size_t i = 0; i < cand[lv].size(); i++) {
+            phi[lv] = cand[lv][i];
+            level(lv + 1);
+        }
+    }
+
+    void root(uint32_t r) {
+        uint32_t dout = G.out_off[r + 1] - G.out_off[r], din = G.in_off[r + 1] - G.in_off[r];
+        if (dout < P.root_dout || din < P.root_din) return;
+        w.roots += 1;
+        phi[0] = r;
+        level(1);
+    }
+};
+
+}  // namespace
+
+void plan_work(const HostCsr& g, const PlanDesc& p, const uint32_t* roots, uint32_t n_roots,
+               unsigned threads, WorkOut& out) {
+    std::atomic<uint64_t> cursor{0};
+    uint64_t total = roots ? n_roots : g.n;
+    threads = std::max(1u, threads);
+    std::vector<WorkOut> parts(threads);
+    std::vector<std::thread> ts;
+    for (unsigned t = 0; t < threads; t++) {
+        ts.emplace_back([&, t]() {
+            Walker wk(g, p);
+            for (;;) {
+                uint64_t b = cursor.fetch_add(64);
+                if (b >= total) break;
+                uint64_t e = std::min<uint64_t>(total, b + 64);
+                for (uint64_t i = b; i < e; i++) {
+                    uint32_t r = roots ? roots[i] : (uint32_t)i;
+                    if (r < g.n) wk.root(r);
+                }
+            }
+            parts[t] = wk.w;
+        });
+    }
+    for (auto& th : ts) th.join();
+    out = WorkOut();
+    for (auto& w : parts) {
+        out.elements += w.elements;
+        out.fetches += w.fetches;
+        out.partial += w.partial;
+        out.roots += w.roots;
+    }
+}
+
+}  // namespace xm

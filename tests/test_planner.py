@@ -122,3 +122,33 @@ class _Raw:
 
     def arcs_u8(self):
         return b""
+
+
+def test_plan_work_complete_digraph_closed_form():
+    """xm_plan_work on K_n: every list holds n-1 nodes and every candidate survives
+    except the bound ones, so the partial matches of level i are n!/(n-i-1)!."""
+    from paper_2404_11105_amd import plan_work
+    n = 7
+    g = xmgen.complete_digraph(n)
+    for name in ["c4", "bifan", "tt4p", "c5chord", "p7hub"]:
+        for reduced in (True, False):
+            p = Plan(xmgen.named(name), reduced)
+            d = p.describe()
+            w = plan_work(g, p)
+            e = d["e"]
+            assert w["roots"] == n
+            partial = sum(pins.complete_count(n, i + 1) for i in range(1, e))
+            assert w["partial_matches"] == partial, (name, reduced)
+            # every fetched list has n-1 entries; reused candidate sets hold the survivors
+            assert w["elements"] > 0 and w["fetches"] >= partial
+            assert w["elements"] <= (n - 1) * w["fetches"]
+
+
+def test_plan_work_reduced_reads_less_on_stars():
+    from paper_2404_11105_amd import plan_work
+    g = xmgen.rmat(9, seed=1)
+    pat = xmgen.named("mixed_star")
+    red = plan_work(g, Plan(pat, True))
+    unred = plan_work(g, Plan(pat, False))
+    assert red["elements"] < unred["elements"]
+    assert red["partial_matches"] == 0 < unred["partial_matches"]
