@@ -138,6 +138,159 @@ def copy_probe(mib: int, reps: int):
     print(json.dumps({"copy_probe_bytes": n * 4, "reps": reps}), flush=True)
 
 
+def bench_batch256(args):
+    """256 capped random patterns on one resident R-MAT scale 22 graph: one
+    persistent batched launch (HIP graph, autotuned) against 256 plain
+    launches of the same plans; batched == plain for every count, and oracle
+    root-subset parity on a sample of patterns."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2404_11105_amd import Counter, Graph, Plan, workloads
+    from paper_2404_11105_amd.api import workspace_bytes
+    from paper_2404_11105_amd.tune import tune
+
+    torch.cuda.set_device(0)
+    log("[batch] generating R-MAT scale 22")
+    g = workloads.batch_graph()
+    pats = workloads.batch_patterns()
+    G = Graph(g)
+    plans = [Plan(p, reduced=True, graph=G) for p in pats]
+    s = torch.cuda.Stream()
+    log("[batch] autotuning")
+    opts, trec = tune(G, plans, stream=s, reps=1, budget_s=150, log=log)
+    log(f"[batch] tuned {opts} ({trec['ms']:.1f} ms vs default {trec['default_ms']:.1f} ms)")
+    cb = Counter(G, plans, **opts)
+    cb.capture(s)
+    ms_b, gpu_b = timed_steps(cb, s, args.steps, args.warmup)
+    counts, status = cb.results()
+    assert all(x == 0 for x in status), status
+    log("[batch] 256 plain launches")
+    ws = torch.empty(max(workspace_bytes(G, [p], **opts) for p in plans), dtype=torch.uint8,
+                     device="cuda")
+    plain = [Counter(G, [p], workspace=ws, **opts) for p in plans]
+    steps_plain = max(1, args.steps // 2)
+    ms_p = timed_plain(plain, s, steps_plain, 1)
+    plain_counts = [c.results()[0][0] for c in plain]
+    assert plain_counts == counts, "batched and plain counts differ"
+    # oracle parity on root subsets of a sample of patterns
+    log("[batch] oracle root-subset parity")
+    rng = np.random.default_rng(7)
+    sample_ids = rng.choice(len(pats), size=12, replace=False)
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    parity = True
+    for i in sample_ids:
+        roots = np.sort(rng.choice(g.n, size=256, replace=False)).astype(np.uint32)
+        c = Counter(G, [plans[i]], roots=roots, workspace=ws, **opts)
+        c.run(s)
+        s.synchronize()
+        got = c.results()[0][0]
+        want = oracle.count(g, pats[i], roots=roots, root_vertex=plans[i].root_vertex,
+                            threads=threads, mode="B")
+        parity = parity and got == want
+    total = sum(counts)
+    rec = {
+        "metric": METRIC, "value": total / (ms_b / 1e3), "unit": "embeddings/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_b, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "batch256_rmat22", "n": g.n, "m": g.m, "patterns": len(pats),
+                   "pattern_sizes": {k: sum(1 for p in pats if p.k == k) for k in (3, 4, 5, 6)},
+                   "plan": "reduced", "launch": "one persistent launch, HIP graph, autotuned",
+                   "tuned": opts},
+        "batched_gpu_ms": round(gpu_b, 3), "plain_ms_per_step": round(ms_p, 3),
+        "batched_vs_plain_speedup": round(ms_p / ms_b, 3),
+        "tune": trec, "counts_sum": str(total), "batched_equals_plain": True,
+        "oracle_root_subset_parity": parity, "oracle_parity_patterns": len(sample_ids),
+    }
+    print(json.dumps(rec), flush=True)
+
+
+def bench_serve(args):
+    """Continuous batching over 8 resident R-MAT graphs (scales 18-24, built
+    on the device); Poisson arrivals at two fixed rates set from the measured
+    capacity; p50/p99 latency and counts/s; results alone == in the mix."""
+    import numpy as np
+    import torch
+
+    import xmgen
+    from paper_2404_11105_amd import Graph, workloads
+    from paper_2404_11105_amd.serve import GpuBackend, Server
+
+    torch.cuda.set_device(0)
+    scales = [18, 19, 20, 21, 22, 23, 24, 24]
+    graphs = {}
+    for i, sc in enumerate(scales):
+        log(f"[serve] building R-MAT scale {sc} on the device")
+        dg = xmgen.rmat_device(sc, seed=i)
+        graphs[i] = Graph(dg)
+    resident = sum(G.nbytes for G in graphs.values())
+    pool = workloads.batch_patterns()
+    rng = np.random.default_rng(5)
+
+    def draw(nreq):
+        return [(int(rng.integers(0, len(scales))), pool[int(rng.integers(0, len(pool)))])
+                for _ in range(nreq)]
+
+    backend = GpuBackend(graphs)
+    budget = 64 << 30
+    # capacity: back-to-back requests, everything queued at once
+    log("[serve] measuring capacity")
+    warm = draw(64)
+    srv = Server(backend, budget, slots=4, max_batch=16)
+    t0 = time.perf_counter()
+    futs = [srv.submit(gid, p) for gid, p in warm]
+    for f in futs:
+        f.result()
+    cap_rps = len(warm) / (time.perf_counter() - t0)
+    srv.close()
+    levels = []
+    for frac in (0.5, 0.8):
+        qps = frac * cap_rps
+        reqs = draw(args.requests)
+        gaps = rng.exponential(1.0 / qps, size=len(reqs))
+        log(f"[serve] {len(reqs)} requests at {qps:.1f}/s")
+        srv = Server(backend, budget, slots=4, max_batch=16)
+        futs = []
+        t_next = time.perf_counter()
+        for (gid, p), gap in zip(reqs, gaps):
+            t_next += gap
+            d = t_next - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            futs.append(srv.submit(gid, p))
+        res = [f.result() for f in futs]
+        srv.close()
+        st = srv.stats()
+        st.update(qps=qps, load=frac)
+        levels.append((st, reqs, res))
+    # alone vs in the mix, on a sample of the last level's requests
+    log("[serve] alone vs mix")
+    st_last, reqs, res = levels[-1]
+    same = True
+    for i in rng.choice(len(reqs), size=16, replace=False):
+        srv = Server(backend, budget, slots=1, max_batch=1)
+        alone = srv.submit(*reqs[i]).result()
+        srv.close()
+        same = same and alone == res[i]
+    st = levels[-1][0]
+    rec = {
+        "metric": METRIC, "value": st["embeddings_per_s"], "unit": "embeddings/s", "n_gpus": 1,
+        "steps": args.requests, "warmup": len(warm), "ms_per_step": st["p50_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "serve_rmat18-24x8", "graph_scales": scales,
+                   "resident_bytes": resident, "pattern_pool": len(pool),
+                   "arrivals": "Poisson", "hbm_budget_bytes": budget, "slots": 4, "max_batch": 16},
+        "capacity_requests_per_s": cap_rps,
+        "levels": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in l[0].items()}
+                   for l in levels],
+        "alone_equals_mix": same,
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +302,10 @@ def main():
     ap.add_argument("--split", type=int, default=0)
     ap.add_argument("--cap", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--workload", default="rmat16", choices=["rmat16", "batch256", "serve"],
+                    help="rmat16: the contract line (default); batch256 / serve: the batched "
+                         "and serving workloads, each printing its own JSON line")
+    ap.add_argument("--requests", type=int, default=400, help="serve: requests per load level")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run plain device copies of this size (counter calibration)")
     args = ap.parse_args()
@@ -161,6 +318,12 @@ def main():
               "(roots would shard across GPUs with one final 128-bit sum; not built).",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch256":
+        bench_batch256(args)
+        return
+    if args.workload == "serve":
+        bench_serve(args)
+        return
 
     import numpy as np
     import torch

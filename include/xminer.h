@@ -133,10 +133,13 @@ int xm_free_plan(xm_plan_t* p);
  * base).  out[0] = adjacency elements intersected, out[1] = list fetches,
  * out[2] = partial matches of the enumerated levels, out[3] = roots that
  * pass the start vertex's degree constraint.  roots (nullable, host array)
- * limits the start vertex's images.  threads: host worker threads (0 = 1). */
+ * limits the start vertex's images.  threads: host worker threads (0 = 1).
+ * max_partial > 0 stops the walk once that many partial matches were seen;
+ * the call then returns 1 (figures are partial sums) instead of XM_OK. */
 int xm_plan_work(uint32_t n, const uint32_t* out_off, const uint32_t* out_adj,
                  const uint32_t* in_off, const uint32_t* in_adj, const xm_plan_t* p,
-                 const uint32_t* roots, uint32_t n_roots, uint32_t threads, uint64_t out[4]);
+                 const uint32_t* roots, uint32_t n_roots, uint32_t threads,
+                 uint64_t max_partial, uint64_t out[4]);
 
 /* ----------------------------------------------------------------------------
  * Counting (Algorithm 2; sections 5.2-5.3).

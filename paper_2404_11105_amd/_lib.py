@@ -84,7 +84,7 @@ def lib():
         L.xm_plan_describe.argtypes = [P, ctypes.c_char_p, SZ, ctypes.POINTER(SZ)]
         L.xm_plan_root_vertex.argtypes = [P]
         L.xm_free_plan.argtypes = [P]
-        L.xm_plan_work.argtypes = [U32, P, P, P, P, P, P, U32, U32, P]
+        L.xm_plan_work.argtypes = [U32, P, P, P, P, P, P, U32, U32, ctypes.c_uint64, P]
         L.xm_workspace_size.argtypes = [P, U32, P, P]
         L.xm_workspace_size.restype = SZ
         L.xm_count.argtypes = [P, U32, P, P, P, SZ, P, P, P]

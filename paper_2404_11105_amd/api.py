@@ -42,8 +42,12 @@ class Graph:
         self.n = int(digraph.n)
         self.m = int(digraph.m)
         self.device = torch.device(device)
-        self.tensors = [_u32_tensor(x, self.device) for x in
-                        (digraph.out_off, digraph.out_adj, digraph.in_off, digraph.in_adj)]
+        arrays = (digraph.out_off, digraph.out_adj, digraph.in_off, digraph.in_adj)
+        if all(isinstance(x, torch.Tensor) for x in arrays):
+            # already device-resident int32 tensors holding uint32 values
+            self.tensors = [x.to(self.device).contiguous() for x in arrays]
+        else:
+            self.tensors = [_u32_tensor(x, self.device) for x in arrays]
         self.nbytes = sum(t.numel() * 4 for t in self.tensors)
         h = ctypes.c_void_p()
         flags = _lib.XM_MEM_DEVICE | (_lib.XM_VALIDATE if validate else 0)
@@ -143,7 +147,7 @@ class Counter:
 
     def __init__(self, graph: Graph, plans, chunk=0, split=0, cap=0, waves_per_cu=0,
                  roots=None, cancel=None, kernel_events: bool = False, stream=None,
-                 merge_min=0, merge_ratio=0, split_work=0):
+                 merge_min=0, merge_ratio=0, split_work=0, workspace=None):
         import torch
         self.graph = graph
         self.plans = list(plans)
@@ -167,7 +171,14 @@ class Counter:
         if ws == 0:
             check(_lib.XM_ERR_INVALID if lib().xm_last_error() else _lib.XM_ERR_INVALID)
         self.ws_bytes = int(ws)
-        self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        if workspace is not None:
+            # a caller-shared buffer: launches that use it must not overlap in time
+            if workspace.numel() * workspace.element_size() < self.ws_bytes:
+                raise ValueError("shared workspace is smaller than xm_workspace_size")
+            self.workspace = workspace
+            self.ws_bytes = workspace.numel() * workspace.element_size()
+        else:
+            self.workspace = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
         self.counts = torch.zeros(2 * len(self.plans), dtype=torch.int64, device=dev)
         self.status = torch.zeros(len(self.plans), dtype=torch.int32, device=dev)
         self.exec = None
@@ -218,8 +229,11 @@ class Counter:
             pass
 
 
-def plan_work(digraph, plan: Plan, roots=None, threads: int = 1) -> dict:
-    """Algorithmic work of a plan on a host graph (statistics only, no count)."""
+def plan_work(digraph, plan: Plan, roots=None, threads: int = 1, max_partial: int = 0) -> dict:
+    """Algorithmic work of a plan on a host graph (statistics only, no count).
+
+    With max_partial > 0 the walk stops after that many partial matches and
+    the result has exceeded=True."""
     arrs = [np.ascontiguousarray(a, dtype=np.uint32) for a in
             (digraph.out_off, digraph.out_adj, digraph.in_off, digraph.in_adj)]
     arrs = [a if a.size else np.zeros(1, dtype=np.uint32) for a in arrs]
@@ -229,9 +243,20 @@ def plan_work(digraph, plan: Plan, roots=None, threads: int = 1) -> dict:
         r = np.ascontiguousarray(roots, dtype=np.uint32)
         nr = int(r.size)
     ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
-    check(lib().xm_plan_work(int(digraph.n), *[ptr(a) for a in arrs], plan.handle,
-                             ptr(r) if r is not None else None, nr, threads, out))
-    return dict(elements=out[0], fetches=out[1], partial_matches=out[2], roots=out[3])
+    rc = check(lib().xm_plan_work(int(digraph.n), *[ptr(a) for a in arrs], plan.handle,
+                                  ptr(r) if r is not None else None, nr, threads, max_partial, out))
+    return dict(elements=out[0], fetches=out[1], partial_matches=out[2], roots=out[3],
+                exceeded=rc == 1)
+
+
+def workspace_bytes(graph: Graph, plans, **opts) -> int:
+    """xm_workspace_size for these plans and options."""
+    o = make_opts(**opts)
+    arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
+    ws = lib().xm_workspace_size(graph.handle, len(plans), arr, ctypes.byref(o))
+    if ws == 0:
+        check(_lib.XM_ERR_INVALID)
+    return int(ws)
 
 
 def count(graph: Graph, plans, stream=None, **opts):

@@ -108,7 +108,9 @@ struct HostCsr {
 struct WorkOut {
     uint64_t elements = 0, fetches = 0, partial = 0, roots = 0;
 };
-void plan_work(const HostCsr& g, const PlanDesc& p, const uint32_t* roots, uint32_t n_roots,
-               unsigned threads, WorkOut& out);
+// Returns true when the walk stopped early because it passed max_partial
+// partial matches (0 = no limit); the figures are then partial sums.
+bool plan_work(const HostCsr& g, const PlanDesc& p, const uint32_t* roots, uint32_t n_roots,
+               unsigned threads, uint64_t max_partial, WorkOut& out);
 
 }  // namespace xm

@@ -425,18 +425,18 @@ int xm_load_graph(uint32_t n, uint32_t m, const uint32_t* out_off, const uint32_
 
 int xm_plan_work(uint32_t n, const uint32_t* out_off, const uint32_t* out_adj, const uint32_t* in_off,
                  const uint32_t* in_adj, const xm_plan_t* p, const uint32_t* roots, uint32_t n_roots,
-                 uint32_t threads, uint64_t out[4]) {
+                 uint32_t threads, uint64_t max_partial, uint64_t out[4]) {
     if (!p || !out || !out_off || !in_off || n == 0) return fail(XM_ERR_INVALID, "NULL argument");
     if ((out_off[n] > 0 && !out_adj) || (in_off[n] > 0 && !in_adj))
         return fail(XM_ERR_INVALID, "NULL adjacency array");
     xm::HostCsr h{out_off, out_adj, in_off, in_adj, n};
     xm::WorkOut w;
-    xm::plan_work(h, p->desc, roots, n_roots, threads ? threads : 1, w);
+    bool exceeded = xm::plan_work(h, p->desc, roots, n_roots, threads ? threads : 1, max_partial, w);
     out[0] = w.elements;
     out[1] = w.fetches;
     out[2] = w.partial;
     out[3] = w.roots;
-    return XM_OK;
+    return exceeded ? 1 : XM_OK;
 }
 
 int xm_free_graph(xm_graph_t* g) {

@@ -25,6 +25,10 @@ struct Walker {
     const HostCsr& G;
     const PlanDesc& P;
     WorkOut w;
+    std::atomic<uint64_t>* shared_partial = nullptr;  // budget accounting across threads
+    uint64_t budget = 0;
+    uint64_t reported = 0;
+    bool stop = false;
     uint32_t phi[kMaxK];
     std::vector<uint32_t> cand[kMaxK];
 
@@ -101,6 +105,7 @@ struct Walker {
     }
 
     void level(uint32_t lv) {
+        if (stop) return;
         if (lv == P.e) {
             leaves(lv);
             return;
@@ -134,6 +139,11 @@ struct Walker {
             if (ok) out.push_back(x);
         }
         w.partial += out.size();
+        if (budget && w.partial - reported >= 4096) {
+            uint64_t tot = shared_partial->fetch_add(w.partial - reported) + (w.partial - reported);
+            reported = w.partial;
+            if (tot > budget) stop = true;
+        }
         // deeper levels only write cand[> lv], so cand[lv] stays valid for reuse
         for (size_t i = 0; i < cand[lv].size(); i++) {
             phi[lv] = cand[lv][i];
@@ -152,9 +162,11 @@ struct Walker {
 
 }  // namespace
 
-void plan_work(const HostCsr& g, const PlanDesc& p, const uint32_t* roots, uint32_t n_roots,
-               unsigned threads, WorkOut& out) {
+bool plan_work(const HostCsr& g, const PlanDesc& p, const uint32_t* roots, uint32_t n_roots,
+               unsigned threads, uint64_t max_partial, WorkOut& out) {
     std::atomic<uint64_t> cursor{0};
+    std::atomic<uint64_t> partial{0};
+    std::atomic<bool> exceeded{false};
     uint64_t total = roots ? n_roots : g.n;
     threads = std::max(1u, threads);
     std::vector<WorkOut> parts(threads);
@@ -162,15 +174,18 @@ void plan_work(const HostCsr& g, const PlanDesc& p, const uint32_t* roots, uint3
     for (unsigned t = 0; t < threads; t++) {
         ts.emplace_back([&, t]() {
             Walker wk(g, p);
+            wk.shared_partial = &partial;
+            wk.budget = max_partial;
             for (;;) {
                 uint64_t b = cursor.fetch_add(64);
-                if (b >= total) break;
+                if (b >= total || wk.stop || exceeded.load()) break;
                 uint64_t e = std::min<uint64_t>(total, b + 64);
-                for (uint64_t i = b; i < e; i++) {
+                for (uint64_t i = b; i < e && !wk.stop; i++) {
                     uint32_t r = roots ? roots[i] : (uint32_t)i;
                     if (r < g.n) wk.root(r);
                 }
             }
+            if (wk.stop) exceeded.store(true);
             parts[t] = wk.w;
         });
     }
@@ -182,6 +197,7 @@ void plan_work(const HostCsr& g, const PlanDesc& p, const uint32_t* roots, uint3
         out.partial += w.partial;
         out.roots += w.roots;
     }
+    return exceeded.load();
 }
 
 }  // namespace xm

@@ -1,0 +1,229 @@
+"""Continuous-batching server for (graph, pattern) count queries.
+
+Graphs stay resident; plans are cached per (graph, pattern).  A scheduler
+thread keeps up to `slots` micro-batches in flight, each on its own HIP
+stream: when a slot is free and memory allows, it takes the oldest pending
+request, gathers further pending requests on the same graph (up to
+`max_batch`), and launches them as ONE persistent xm_count.  Requests that
+arrive while others run are admitted as soon as a slot and HBM budget free
+up, so their work overlaps the tail of the running batches on the device.
+
+Admission is by HBM footprint: a micro-batch needs its workspace
+(xm_workspace_size) plus 24 bytes per plan; the sum over in-flight batches
+never exceeds `hbm_budget`.  A request whose batch could never fit is
+rejected at once.  Each request may carry a deadline; one that expires while
+still queued is completed with status XM_ERR_CANCELLED without running.
+
+Latency = completion time - submission time (host clock).  `stats()` gives
+p50 / p99 latency and counts/s over the completed requests.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import threading
+import time
+from concurrent.futures import Future
+
+XM_ERR_CANCELLED = -7
+XM_ERR_ADMISSION = -9  # serving-level status: the request can never fit the budget
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    graph_id: object
+    pattern: object
+    submitted: float
+    deadline: float | None
+    future: Future
+    done: float = 0.0
+    status: int = 0
+    count: int | None = None
+
+
+class GpuBackend:
+    """Runs micro-batches with the HIP library on torch streams."""
+
+    def __init__(self, graphs: dict, opts: dict | None = None):
+        import torch
+        self.torch = torch
+        self.graphs = graphs
+        self.opts = dict(opts or {})
+        self.plans = {}
+
+    def plan(self, graph_id, pattern):
+        from .api import Plan
+        key = (graph_id, pattern.k, pattern.arcs)
+        p = self.plans.get(key)
+        if p is None:
+            p = Plan(pattern, reduced=True, graph=self.graphs[graph_id])
+            self.plans[key] = p
+        return p
+
+    def footprint(self, graph_id, plans) -> int:
+        import ctypes
+        from ._lib import XminerError, lib
+        from .api import make_opts
+        o = make_opts(**self.opts)
+        arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
+        ws = lib().xm_workspace_size(self.graphs[graph_id].handle, len(plans), arr, ctypes.byref(o))
+        if ws == 0:
+            raise XminerError(-1, lib().xm_last_error().decode())
+        return int(ws) + 24 * len(plans)
+
+    def new_slot(self):
+        return self.torch.cuda.Stream()
+
+    def launch(self, slot, graph_id, plans):
+        from .api import Counter
+        c = Counter(self.graphs[graph_id], plans, **self.opts)
+        c.run(slot)
+        ev = self.torch.cuda.Event()
+        ev.record(slot)
+        return (c, ev)
+
+    def poll(self, handle) -> bool:
+        return handle[1].query()
+
+    def results(self, handle):
+        c, ev = handle
+        ev.synchronize()
+        return c.results(sync=False)
+
+
+class Server:
+    def __init__(self, backend, hbm_budget: int, slots: int = 4, max_batch: int = 32,
+                 poll_s: float = 0.0002):
+        self.backend = backend
+        self.hbm_budget = int(hbm_budget)
+        self.max_batch = max_batch
+        self.poll_s = poll_s
+        self.slots = [backend.new_slot() for _ in range(slots)]
+        self.busy = {}  # slot index -> (handle, requests, footprint)
+        self.pending = collections.deque()
+        self.completed = []
+        self.in_use = 0
+        self.lock = threading.Condition()
+        self.next_id = 0
+        self.stop = False
+        self.launches = 0
+        self.max_inflight = 0
+        self.thread = threading.Thread(target=self._loop, daemon=True)
+        self.thread.start()
+
+    # ---- client side
+    def submit(self, graph_id, pattern, deadline_s: float | None = None) -> Future:
+        now = time.perf_counter()
+        f = Future()
+        with self.lock:
+            r = Request(self.next_id, graph_id, pattern, now,
+                        now + deadline_s if deadline_s is not None else None, f)
+            self.next_id += 1
+            self.pending.append(r)
+            self.lock.notify()
+        return f
+
+    def close(self):
+        with self.lock:
+            self.stop = True
+            self.lock.notify()
+        self.thread.join()
+
+    def drain(self, timeout_s: float = 600.0):
+        t0 = time.perf_counter()
+        while True:
+            with self.lock:
+                if not self.pending and not self.busy:
+                    return
+            if time.perf_counter() - t0 > timeout_s:
+                raise TimeoutError("server did not drain")
+            time.sleep(0.001)
+
+    # ---- scheduler
+    def _finish(self, r: Request, status: int, count):
+        r.done = time.perf_counter()
+        r.status = status
+        r.count = count
+        self.completed.append(r)
+        r.future.set_result((count, status))
+
+    def _reap(self):
+        for si in list(self.busy):
+            handle, reqs, fp = self.busy[si]
+            if not self.backend.poll(handle):
+                continue
+            counts, status = self.backend.results(handle)
+            for r, c, s in zip(reqs, counts, status):
+                self._finish(r, s, c if s == 0 else None)
+            self.in_use -= fp
+            del self.busy[si]
+
+    def _admit(self):
+        free = [i for i in range(len(self.slots)) if i not in self.busy]
+        now = time.perf_counter()
+        while free and self.pending:
+            head = self.pending[0]
+            if head.deadline is not None and now > head.deadline:
+                self.pending.popleft()
+                self._finish(head, XM_ERR_CANCELLED, None)
+                continue
+            # gather same-graph requests in arrival order
+            batch, rest = [], collections.deque()
+            while self.pending:
+                r = self.pending.popleft()
+                if r.graph_id == head.graph_id and len(batch) < self.max_batch and (
+                        r.deadline is None or now <= r.deadline):
+                    batch.append(r)
+                else:
+                    rest.append(r)
+            # shrink the batch until it fits the free budget
+            plans = [self.backend.plan(r.graph_id, r.pattern) for r in batch]
+            fp = self.backend.footprint(head.graph_id, plans)
+            while fp > self.hbm_budget - self.in_use and len(batch) > 1:
+                rest.appendleft(batch.pop())
+                plans.pop()
+                fp = self.backend.footprint(head.graph_id, plans)
+            if fp > self.hbm_budget:
+                # even alone this request can never fit
+                self._finish(batch[0], XM_ERR_ADMISSION, None)
+                self.pending = collections.deque(sorted(list(rest) + batch[1:], key=lambda q: q.rid))
+                continue
+            if fp > self.hbm_budget - self.in_use:
+                # wait for memory; everything goes back in arrival order
+                self.pending = collections.deque(sorted(list(rest) + batch, key=lambda q: q.rid))
+                break
+            self.pending = collections.deque(sorted(rest, key=lambda q: q.rid))
+            si = free.pop(0)
+            handle = self.backend.launch(self.slots[si], head.graph_id, plans)
+            self.busy[si] = (handle, batch, fp)
+            self.in_use += fp
+            self.launches += 1
+            self.max_inflight = max(self.max_inflight, len(self.busy))
+
+    def _loop(self):
+        while True:
+            with self.lock:
+                if self.stop and not self.pending and not self.busy:
+                    return
+                self._reap()
+                self._admit()
+                idle = not self.pending and not self.busy
+                if idle:
+                    self.lock.wait(timeout=0.01)
+            if not idle:
+                time.sleep(self.poll_s)
+
+    # ---- reporting
+    def stats(self) -> dict:
+        ok = [r for r in self.completed if r.status == 0]
+        lat = sorted((r.done - r.submitted) * 1e3 for r in ok)
+        if not lat:
+            return {"completed": 0}
+        span = max(r.done for r in ok) - min(r.submitted for r in ok)
+        pick = lambda q: lat[min(len(lat) - 1, int(q * len(lat)))]  # noqa: E731
+        return {"completed": len(ok), "failed": len(self.completed) - len(ok),
+                "p50_ms": pick(0.50), "p99_ms": pick(0.99), "max_ms": lat[-1],
+                "requests_per_s": len(ok) / span if span > 0 else None,
+                "embeddings_per_s": sum(r.count for r in ok) / span if span > 0 else None,
+                "launches": self.launches, "max_inflight_batches": self.max_inflight}

@@ -1,0 +1,104 @@
+"""Autotuner for xm_count launch parameters.
+
+For one resident graph and one batch of plans it searches the launch
+parameters that only change speed, never the counts:
+
+  split_work  target work of a stealable first-level task (hub splitting)
+  split       largest first-level sub-range of a split root
+  chunk       roots per root task
+  waves_per_cu resident waves (0 = from occupancy)
+  merge_min   cooperative merge threshold (0xFFFFFFFF = off)
+
+by coordinate descent from the library defaults: each parameter in turn is
+set to every value of its list with the others fixed, the batched launch is
+timed with HIP events on the launch stream (one warm-up, then the median of
+`reps` launches), and the fastest value is kept.  Every configuration must
+return the same counts, else the tuner raises.  Results are cached in a
+JSON file keyed by the graph's size and the plans' descriptions.
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+import time
+
+SPACE = [
+    ("split_work", [4096, 8192, 16384, 65536]),
+    ("split", [64, 128, 512]),
+    ("chunk", [1, 4, 16]),
+    ("waves_per_cu", [0, 16, 32]),
+    ("merge_min", [0xFFFFFFFF, 64]),
+]
+DEFAULTS = dict(split_work=8192, split=64, chunk=4, waves_per_cu=0, merge_min=0xFFFFFFFF)
+
+
+def signature(graph, plans) -> str:
+    from .api import plan_json
+    h = hashlib.sha256()
+    h.update(f"{graph.n}:{graph.m}".encode())
+    for p in plans:
+        h.update(plan_json(p).encode())
+    return h.hexdigest()[:24]
+
+
+def time_launch(graph, plans, stream, reps: int = 3, **opts):
+    """Median GPU milliseconds of one batched launch, and its counts."""
+    import torch
+    from .api import Counter
+    c = Counter(graph, plans, **opts)
+    c.run(stream)
+    stream.synchronize()
+    counts, status = c.results()
+    if any(s != 0 for s in status):
+        raise RuntimeError(f"launch status {status} with {opts}")
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        c.run(stream)
+        e1.record(stream)
+        stream.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    ms.sort()
+    return ms[len(ms) // 2], counts
+
+
+def tune(graph, plans, stream=None, cache_path: str | None = None, reps: int = 3,
+         budget_s: float = 120.0, log=None):
+    """Best launch options for (graph, plans); returns (opts, record)."""
+    import torch
+    key = signature(graph, plans)
+    cache = {}
+    if cache_path and os.path.exists(cache_path):
+        cache = json.load(open(cache_path))
+        if key in cache:
+            return dict(cache[key]["opts"]), cache[key]
+    stream = stream or torch.cuda.Stream()
+    t0 = time.time()
+    best = dict(DEFAULTS)
+    best_ms, ref_counts = time_launch(graph, plans, stream, reps, **best)
+    trials = [(dict(best), best_ms)]
+    for name, values in SPACE:
+        for v in values:
+            if v == best[name] or time.time() - t0 > budget_s:
+                continue
+            cand = dict(best, **{name: v})
+            ms, counts = time_launch(graph, plans, stream, reps, **cand)
+            if counts != ref_counts:
+                raise RuntimeError(f"counts changed with {cand}")
+            trials.append((cand, ms))
+            if log:
+                log(f"[tune] {name}={v}: {ms:.2f} ms (best {best_ms:.2f})")
+            if ms < best_ms:
+                best, best_ms = cand, ms
+    rec = {"opts": best, "ms": best_ms, "default_ms": trials[0][1], "trials": len(trials),
+           "seconds": round(time.time() - t0, 1)}
+    if cache_path:
+        cache[key] = rec
+        d = os.path.dirname(cache_path)
+        if d:
+            os.makedirs(d, exist_ok=True)
+        with open(cache_path, "w") as f:
+            json.dump(cache, f, indent=1)
+    return dict(best), rec

@@ -75,10 +75,13 @@ def rmat20_subset():
     """Root-subset parity at scale 20: exact partial sums over listed roots."""
     g = xmgen.rmat(20, seed=0)
     deg = g.out_deg() + g.in_deg()
-    hubs = np.argsort(-deg, kind="stable")[:16]
+    # mid-degree roots (ranks 2000-2015) plus a seeded uniform sample; the
+    # largest hubs (~40K arcs) would take the oracle hours per pattern
+    order = np.argsort(-deg, kind="stable")
+    mids = order[2000:2016]
     rng = np.random.default_rng(20)
     sample = rng.choice(g.n, size=512, replace=False)
-    roots = np.unique(np.concatenate([hubs, sample])).astype(np.uint32)
+    roots = np.unique(np.concatenate([mids, sample])).astype(np.uint32)
     res = {}
     for p, rv in [("tt4p", 0), ("c5chord", 0)]:
         t = time.time()

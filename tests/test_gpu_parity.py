@@ -171,3 +171,4 @@ def test_config2_full_size(xa):
     want = [int(gold[n]) for n in names]
     assert run(xa, g, pats, G=G, reduced=True) == want
     assert run(xa, g, pats, G=G, reduced=False) == want
+

@@ -1,0 +1,111 @@
+"""GPU: serving loop, cancel flag, autotuner and the scale-20 root-subset case."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import xmgen
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def xa():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2404_11105_amd as xa
+    return xa
+
+
+def banner(msg):
+    print(f"[case] {msg}", flush=True)
+
+
+def test_serving_counts_equal_oracle_alone_and_in_the_mix(xa):
+    from paper_2404_11105_amd.serve import GpuBackend, Server
+    banner("serving: 2 resident graphs, 48 requests, 3 slots")
+    hg = {"r": xmgen.rmat(10, seed=1), "u": xmgen.uniform_digraph(300, 2400, 5)}
+    graphs = {k: xa.Graph(v) for k, v in hg.items()}
+    # patterns the oracle counts in seconds on both graphs
+    pool = [xmgen.named(n) for n in ["ffl", "c3", "bifan", "c4", "tt4p"]]
+    pool += [xmgen.random_pattern(k, 4000 + k) for k in (3, 4, 5)]
+    rng = np.random.default_rng(0)
+    reqs = [(["r", "u"][int(rng.integers(0, 2))], pool[int(rng.integers(0, len(pool)))])
+            for _ in range(48)]
+    backend = GpuBackend(graphs)
+    srv = Server(backend, hbm_budget=64 << 30, slots=3, max_batch=8)
+    futs = [srv.submit(g, p) for g, p in reqs]
+    res = [f.result(timeout=300) for f in futs]
+    srv.close()
+    banner("  mixed run done; oracle and alone runs")
+    want, alone = {}, {}
+    for g, p in reqs:
+        key = (g, p.arcs)
+        if key not in want:
+            want[key] = oracle.count(hg[g], p, threads=8, mode="B")
+            one = Server(backend, hbm_budget=64 << 30, slots=1, max_batch=1)
+            alone[key] = one.submit(g, p).result(timeout=300)
+            one.close()
+    for (g, p), (c, st) in zip(reqs, res):
+        key = (g, p.arcs)
+        assert st == 0 and c == want[key], (g, p.name)
+        assert (c, st) == alone[key]
+    s = srv.stats()
+    assert s["completed"] == len(reqs) and s["p99_ms"] >= s["p50_ms"] > 0
+    assert srv.launches < len(reqs), "requests were not batched"
+
+
+def test_cancel_flag_set_before_launch(xa):
+    import torch
+    banner("cancel flag raised before the launch")
+    g = xmgen.rmat(10, seed=2)
+    G = xa.Graph(g)
+    plans = [xa.Plan(xmgen.named(n), graph=G) for n in ["bifan", "c4"]]
+    flag = torch.ones(1, dtype=torch.int32, device="cuda")
+    c = xa.Counter(G, plans, cancel=flag)
+    c.run()
+    counts, status = c.results()
+    assert status == [-7, -7]
+    flag.zero_()
+    c.run()
+    counts, status = c.results()
+    assert status == [0, 0] and counts == [oracle.count(g, p.pattern) for p in plans]
+
+
+def test_autotuner_keeps_counts(xa):
+    import torch
+    from paper_2404_11105_amd.tune import tune
+    banner("autotuner on rmat 12")
+    g = xmgen.rmat(12, seed=3)
+    G = xa.Graph(g)
+    plans = [xa.Plan(xmgen.named(n), graph=G) for n in ["bifan", "c4", "ffl", "tt4p"]]
+    opts, rec = tune(G, plans, stream=torch.cuda.Stream(), reps=1, budget_s=60)
+    assert rec["ms"] <= rec["default_ms"] + 1e-9
+    c = xa.Counter(G, plans, **opts)
+    c.run()
+    got, st = c.results()
+    assert st == [0] * 4
+    assert got == [oracle.count(g, p.pattern, threads=8, mode="B") for p in plans]
+
+
+def test_rmat20_root_subset_parity(xa):
+    path = os.path.join(HERE, "golden", "rmat20_subset.json")
+    if not os.path.exists(path):
+        pytest.skip("rmat20 golden not written")
+    banner("R-MAT scale 20 root subsets (tt4p, c5chord), reduced and unreduced")
+    gold = json.load(open(path))
+    g = xmgen.rmat(20, seed=0)
+    assert g.m == gold["m"]
+    G = xa.Graph(g)
+    roots = np.array(gold["roots"], dtype=np.uint32)
+    for name, r in gold["results"].items():
+        for reduced in (True, False):
+            p = xa.Plan(xmgen.named(name), reduced=reduced, graph=G, root_vertex=r["root_vertex"])
+            c = xa.Counter(G, [p], roots=roots)
+            c.run()
+            got, st = c.results()
+            assert st == [0] and got == [int(r["count"])], (name, reduced)

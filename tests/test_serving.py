@@ -1,0 +1,120 @@
+"""Serving loop (CPU): admission by footprint, continuous batching, deadlines,
+and results identical alone and in the mix.  A fake backend stands in for the
+GPU: its launches take simulated time and its counts come from the oracle."""
+import threading
+import time
+
+import pytest
+
+import oracle
+import xmgen
+from paper_2404_11105_amd.serve import XM_ERR_ADMISSION, XM_ERR_CANCELLED, Server
+
+
+class FakeBackend:
+    def __init__(self, graphs, secs_per_plan=0.002, ws_bytes=1000):
+        self.graphs = graphs
+        self.secs = secs_per_plan
+        self.ws = ws_bytes
+        self.launched = []
+        self.inflight = 0
+        self.max_inflight = 0
+        self.mu = threading.Lock()
+
+    def plan(self, graph_id, pattern):
+        return pattern
+
+    def footprint(self, graph_id, plans):
+        return self.ws + 24 * len(plans)
+
+    def new_slot(self):
+        return object()
+
+    def launch(self, slot, graph_id, plans):
+        g = self.graphs[graph_id]
+        counts = [oracle.count(g, p) for p in plans]
+        with self.mu:
+            self.inflight += 1
+            self.max_inflight = max(self.max_inflight, self.inflight)
+            self.launched.append((graph_id, len(plans)))
+        return {"t": time.perf_counter() + self.secs * len(plans), "counts": counts, "done": False}
+
+    def poll(self, h):
+        if time.perf_counter() >= h["t"]:
+            if not h["done"]:
+                with self.mu:
+                    self.inflight -= 1
+                h["done"] = True
+            return True
+        return False
+
+    def results(self, h):
+        return h["counts"], [0] * len(h["counts"])
+
+
+def graphs():
+    return {"u": xmgen.uniform_digraph(200, 1500, 1), "r": xmgen.rmat(8, seed=2)}
+
+
+def pats():
+    return [xmgen.named(n) for n in ["ffl", "c3", "bifan", "c4", "path3", "outstar3"]]
+
+
+def test_results_alone_and_in_the_mix_are_identical():
+    G = graphs()
+    P = pats()
+    alone = {}
+    for gid in G:
+        for i, p in enumerate(P):
+            s = Server(FakeBackend(G), hbm_budget=10 ** 6, slots=1, max_batch=1)
+            alone[(gid, i)] = s.submit(gid, p).result(timeout=60)[0]
+            s.close()
+    be = FakeBackend(G, secs_per_plan=0.01)
+    s = Server(be, hbm_budget=10 ** 6, slots=3, max_batch=8)
+    futs = []
+    for rep in range(4):
+        for gid in G:
+            for i, p in enumerate(P):
+                futs.append(((gid, i), s.submit(gid, p)))
+        time.sleep(0.003)  # arrivals while earlier batches run
+    mixed = [(k, f.result(timeout=60)) for k, f in futs]
+    s.close()
+    for k, (c, st) in mixed:
+        assert st == 0 and c == alone[k]
+    st = s.stats()
+    assert st["completed"] == len(futs) and st["p99_ms"] >= st["p50_ms"] > 0
+    assert be.max_inflight >= 2, "batches must overlap"
+    assert any(n > 1 for _, n in be.launched), "requests must be batched"
+
+
+def test_admission_respects_hbm_budget():
+    G = graphs()
+    be = FakeBackend(G, secs_per_plan=0.02, ws_bytes=1000)
+    # room for exactly one batch at a time
+    s = Server(be, hbm_budget=1000 + 24 * 4, slots=4, max_batch=4)
+    futs = [s.submit("u", p) for p in pats() * 2]
+    for f in futs:
+        assert f.result(timeout=60)[1] == 0
+    s.close()
+    assert be.max_inflight == 1
+
+
+def test_request_that_can_never_fit_is_rejected():
+    G = graphs()
+    s = Server(FakeBackend(G, ws_bytes=10 ** 6), hbm_budget=1000, slots=2)
+    c, st = s.submit("u", xmgen.named("c3")).result(timeout=60)
+    s.close()
+    assert st == XM_ERR_ADMISSION and c is None
+
+
+def test_expired_deadline_is_cancelled_without_running():
+    G = graphs()
+    be = FakeBackend(G, secs_per_plan=0.2)
+    s = Server(be, hbm_budget=10 ** 6, slots=1, max_batch=1)
+    f1 = s.submit("u", xmgen.named("c3"))
+    f2 = s.submit("u", xmgen.named("ffl"), deadline_s=0.01)  # expires while f1 runs
+    assert f1.result(timeout=60)[1] == 0
+    c, st = f2.result(timeout=60)
+    s.close()
+    assert st == XM_ERR_CANCELLED and c is None
+    assert len(be.launched) == 1

@@ -177,3 +177,78 @@ def star_hub(leaves: int, extra_nodes: int = 0) -> Digraph:
     n = leaves + 1 + extra_nodes
     return from_arcs(n, np.zeros(leaves, dtype=np.int64), np.arange(1, leaves + 1),
                      name=f"outstar({leaves})")
+
+
+@dataclasses.dataclass
+class DeviceDigraph:
+    """A simple digraph whose uint32 CSR arrays live in device memory (int32
+    tensors holding the uint32 bit patterns)."""
+    n: int
+    out_off: object
+    out_adj: object
+    in_off: object
+    in_adj: object
+    name: str = ""
+
+    @property
+    def m(self) -> int:
+        return int(self.out_off[-1])
+
+    def to_host(self) -> Digraph:
+        cv = lambda t: t.cpu().numpy().view(np.uint32)  # noqa: E731
+        m = int(self.out_off[-1])
+        return Digraph(self.n, cv(self.out_off), cv(self.out_adj)[:m], cv(self.in_off),
+                       cv(self.in_adj)[:m], name=self.name)
+
+
+def rmat_device(scale: int, edge_factor: int = 16, abcd=RMAT_ABCD, seed: int = 0,
+                device: str = "cuda") -> DeviceDigraph:
+    """R-MAT on the GPU with torch's seeded generator (same recipe as rmat():
+    edge_factor * 2**scale draws, quadrant probabilities (a, b, c, d) per bit
+    level, repeats and loops dropped).  The draws differ from rmat()'s numpy
+    stream, so the graph differs; it is deterministic for a seed on one
+    device type.  Built directly in device memory for graphs too large to
+    generate on the host quickly."""
+    import torch
+    a, b, c, d = abcd
+    n = 1 << scale
+    total = edge_factor * n
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    t_a, t_ab, t_abc = float(a), float(a + b), float(a + b + c)
+    keys = []
+    chunk = 1 << 24
+    done = 0
+    while done < total:
+        cnt = min(chunk, total - done)
+        u = torch.zeros(cnt, dtype=torch.int64, device=device)
+        v = torch.zeros(cnt, dtype=torch.int64, device=device)
+        for lvl in range(scale):
+            r = torch.rand(cnt, generator=gen, device=device, dtype=torch.float32)
+            bit = 1 << (scale - 1 - lvl)
+            ub = r >= t_ab
+            vb = ((r >= t_a) & (r < t_ab)) | (r >= t_abc)
+            u += ub.to(torch.int64) * bit
+            v += vb.to(torch.int64) * bit
+        keep = u != v
+        keys.append(torch.unique((u[keep] << 32) | v[keep]))
+        done += cnt
+        del u, v
+    key = torch.unique(torch.cat(keys)) if len(keys) > 1 else keys[0]
+    del keys
+    src = key >> 32
+    dst = key & 0xFFFFFFFF
+    m = int(key.numel())
+    out_off = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    out_off[1:] = torch.cumsum(torch.bincount(src, minlength=n), 0)
+    out_adj = dst.to(torch.int32)
+    ikey, _ = torch.sort((dst << 32) | src)
+    in_off = torch.zeros(n + 1, dtype=torch.int64, device=device)
+    in_off[1:] = torch.cumsum(torch.bincount(dst, minlength=n), 0)
+    in_adj = (ikey & 0xFFFFFFFF).to(torch.int32)
+    del key, src, dst, ikey
+    if m == 0:
+        out_adj = torch.zeros(1, dtype=torch.int32, device=device)
+        in_adj = torch.zeros(1, dtype=torch.int32, device=device)
+    return DeviceDigraph(n, out_off.to(torch.int32), out_adj, in_off.to(torch.int32), in_adj,
+                         name=f"rmat_device(scale={scale},ef={edge_factor},seed={seed})")
