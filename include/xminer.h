@@ -162,7 +162,7 @@ int xm_plan_work(uint32_t n, const uint32_t* out_off, const uint32_t* out_adj,
 typedef struct xm_count_opts {
     uint32_t struct_size;   /* sizeof(xm_count_opts) */
     uint32_t flags;         /* reserved, must be 0 */
-    uint32_t chunk;         /* roots taken per work grab (default 4, <= 64) */
+    uint32_t chunk;         /* roots taken per work grab (default 1, <= 64) */
     uint32_t split;         /* a root whose first-level candidate list has L1
                                entries is split into stealable sub-ranges of
                                min(split, split_work / L1) entries (at least 1)
@@ -179,7 +179,7 @@ typedef struct xm_count_opts {
     /* cancel flag: device int32; when it becomes nonzero, waves stop taking
        new work and the status of unfinished plans is XM_ERR_CANCELLED. */
     const int32_t* cancel_dev;
-    uint32_t split_work;    /* see split (default 8192, >= 4096) */
+    uint32_t split_work;    /* see split (default 4096, >= 4096) */
     /* single-leaf intersections whose two lists are both at least merge_min
        long (default 0xFFFFFFFF: off) and within merge_ratio of each
        other (default 16) are counted by a wave-cooperative merge instead of

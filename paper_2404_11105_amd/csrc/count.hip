@@ -106,11 +106,11 @@ struct Lds {
     uint32_t* mbuf;      // [kMergeChunk]: probe-list chunk of the cooperative merge
 };
 
-__device__ __forceinline__ Lds carve(uint32_t* w, uint32_t maxc) {
+__device__ __forceinline__ Lds carve(uint32_t* w, uint32_t rows, uint32_t maxc, bool merge) {
     Lds s;
     s.bound = w;
-    s.anc = w + kMaxK * 64;
-    uint32_t* q = w + 2 * kMaxK * 64;
+    s.anc = w + rows * 64;
+    uint32_t* q = w + 2 * rows * 64;
     s.base_off = q;
     s.base_len = q + 64;
     s.base_kind = q + 128;
@@ -121,7 +121,7 @@ __device__ __forceinline__ Lds carve(uint32_t* w, uint32_t maxc) {
     s.chk_len = q + maxc * 64;
     q += 2 * maxc * 64;
     s.mbuf = q;
-    q += kMergeChunk;
+    q += merge ? kMergeChunk : 0;
     s.st = q;
     s.hist = q + 32;
     return s;
@@ -265,6 +265,28 @@ __device__ __forceinline__ uint32_t find_parent(const Lds& s, uint32_t np, uint3
     return lo;
 }
 
+// Two independent sorted-list searches interleaved step by step, so each lane
+// keeps two loads in flight instead of one dependent chain.
+__device__ __forceinline__ void contains2(const uint32_t* __restrict__ A, uint32_t la, uint32_t xa, bool& fa,
+                                          const uint32_t* __restrict__ B, uint32_t lb, uint32_t xb, bool& fb) {
+    uint32_t ba = 0, na = fa ? la : 0, bb = 0, nb = fb ? lb : 0;
+    while (na > 1 || nb > 1) {
+        const uint32_t ha = na >> 1, hb = nb >> 1;
+        const uint32_t va = na > 1 ? A[ba + ha] : 0u;
+        const uint32_t vb = nb > 1 ? B[bb + hb] : 0u;
+        if (na > 1) {
+            ba = (va <= xa) ? ba + ha : ba;
+            na -= ha;
+        }
+        if (nb > 1) {
+            bb = (vb <= xb) ? bb + hb : bb;
+            nb -= hb;
+        }
+    }
+    fa = fa && la > 0 && A[ba] == xa;
+    fb = fb && lb > 0 && B[bb] == xb;
+}
+
 __device__ __forceinline__ bool check_elem(const Ctx& C, const LevelDesc& D, uint32_t lv, uint32_t j,
                                            uint32_t x) {
     const DevGraph& g = C.a->g;
@@ -281,6 +303,33 @@ __device__ __forceinline__ bool check_elem(const Ctx& C, const LevelDesc& D, uin
         if (l != kSkip) ok = contains(adj_of(g, D.cons_dir[c]) + C.s.chk_off[c * 64 + j], l, x);
     }
     return ok;
+}
+
+// check_elem for two elements at once (oka / okb: in = element valid, out = passes).
+__device__ __forceinline__ void check_pair(const Ctx& C, const LevelDesc& D, uint32_t lv, uint32_t ja,
+                                           uint32_t xa, bool& oka, uint32_t jb, uint32_t xb, bool& okb) {
+    const DevGraph& g = C.a->g;
+    const uint32_t inj = D.inj;
+    for (uint32_t l = 0; l < lv; l++)
+        if ((inj >> l) & 1u) {
+            oka = oka && (xa != C.s.bound[l * 64 + ja]);
+            okb = okb && (xb != C.s.bound[l * 64 + jb]);
+        }
+    if (D.deg_check) {
+        uint2 da = oka ? g.deg[xa] : make_uint2(0, 0);
+        uint2 db = okb ? g.deg[xb] : make_uint2(0, 0);
+        oka = oka && da.x >= D.dmin_out && da.y >= D.dmin_in;
+        okb = okb && db.x >= D.dmin_out && db.y >= D.dmin_in;
+    }
+    for (uint32_t c = 0; c < D.n_cons; c++) {
+        const uint32_t lA = C.s.chk_len[c * 64 + ja], lB = C.s.chk_len[c * 64 + jb];
+        bool fa = oka && lA != kSkip, fb = okb && lB != kSkip;
+        if (!(fa || fb)) continue;
+        const uint32_t* adj = adj_of(g, D.cons_dir[c]);
+        contains2(adj + C.s.chk_off[c * 64 + ja], lA, xa, fa, adj + C.s.chk_off[c * 64 + jb], lB, xb, fb);
+        if (oka && lA != kSkip) oka = fa;
+        if (okb && lB != kSkip) okb = fb;
+    }
 }
 
 // Membership of x in leaf signature s for window parent j (constraints only;
@@ -332,24 +381,37 @@ __device__ uint32_t expand(Ctx& C, uint32_t lv) {
     Lvl Fo = lvl_arrays(C.scr, cap, lv);
     uint32_t nout = 0;
     const uint32_t reuse = D.reuse;
-    for (uint32_t t0 = 0; t0 < T; t0 += 64) {
-        uint32_t gi = t0 + lane;
-        bool ok = gi < T;
-        uint32_t j = 0, x = 0;
-        if (ok) {
-            j = find_parent(C.s, np, gi);
-            uint32_t local = gi - (j ? C.s.incl[j - 1] : 0) + (j == 0 ? pofs : 0);
-            x = base_elem(C, j, local, reuse);
-            ok = check_elem(C, D, lv, j, x);
+    // two tiles per step: survivors of tile a are written before those of
+    // tile b, so each parent's children stay contiguous and in order
+    for (uint32_t t0 = 0; t0 < T; t0 += 128) {
+        const uint32_t ga = t0 + lane, gb = t0 + 64 + lane;
+        bool oka = ga < T, okb = gb < T;
+        uint32_t ja = 0, xa = 0, jb = 0, xb = 0;
+        if (oka) {
+            ja = find_parent(C.s, np, ga);
+            xa = base_elem(C, ja, ga - (ja ? C.s.incl[ja - 1] : 0) + (ja == 0 ? pofs : 0), reuse);
         }
-        uint64_t m = __ballot(ok);
-        if (ok) {
-            uint32_t pos = nout + rank_below(m);
-            Fo.node[pos] = x;
-            Fo.parent[pos] = cur + j;
-            if (seg) atomicAdd(&C.s.segcnt[j], 1u);
+        if (okb) {
+            jb = find_parent(C.s, np, gb);
+            xb = base_elem(C, jb, gb - (jb ? C.s.incl[jb - 1] : 0) + (jb == 0 ? pofs : 0), reuse);
         }
-        nout += (uint32_t)__popcll(m);
+        check_pair(C, D, lv, ja, xa, oka, jb, xb, okb);
+        const uint64_t ma = __ballot(oka);
+        if (oka) {
+            const uint32_t pos = nout + rank_below(ma);
+            Fo.node[pos] = xa;
+            Fo.parent[pos] = cur + ja;
+            if (seg) atomicAdd(&C.s.segcnt[ja], 1u);
+        }
+        nout += (uint32_t)__popcll(ma);
+        const uint64_t mb = __ballot(okb);
+        if (okb) {
+            const uint32_t pos = nout + rank_below(mb);
+            Fo.node[pos] = xb;
+            Fo.parent[pos] = cur + jb;
+            if (seg) atomicAdd(&C.s.segcnt[jb], 1u);
+        }
+        nout += (uint32_t)__popcll(mb);
     }
     wave_sync();
     if (seg) {
@@ -389,8 +451,8 @@ __device__ uint32_t expand(Ctx& C, uint32_t lv) {
 // every matching pair is seen exactly once.  Reads are coalesced and no
 // dependent global search is needed (merge path for balanced list sizes).
 __device__ uint32_t merge_count(const Lds& s, const uint32_t* __restrict__ A, uint32_t na,
-                                const uint32_t* __restrict__ B, uint32_t nb, const uint32_t* excl,
-                                uint32_t n_excl, uint32_t lane) {
+                                const uint32_t* __restrict__ B, uint32_t nb, uint32_t inj, uint32_t nbound,
+                                uint32_t j, uint32_t lane) {
     constexpr uint32_t U = kMergeChunk / 64;
     uint32_t ia = 0, ib = 0, cnt = 0;
     while (ia < na && ib < nb) {
@@ -418,7 +480,8 @@ __device__ uint32_t merge_count(const Lds& s, const uint32_t* __restrict__ A, ui
                     n -= h;
                 }
                 bool ok = s.mbuf[base] == x;
-                for (uint32_t t = 0; t < n_excl; t++) ok = ok && (x != excl[t]);
+                for (uint32_t t = 0; t < nbound; t++)
+                    if ((inj >> t) & 1u) ok = ok && (x != s.bound[t * 64 + j]);
                 cnt += ok ? 1u : 0u;
             }
         }
@@ -509,23 +572,40 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
             const uint8_t implied = P->sig_implied[s];
             const uint8_t test = P->sig_test[s];
             const uint32_t below = (1u << s) - 1u;
-            for (uint32_t t0 = 0; t0 < T; t0 += 64) {
-                uint32_t gi = t0 + lane;
-                bool ok = gi < T;
-                uint32_t j = 0, x = 0;
-                if (ok) {
-                    j = find_parent(C.s, np, gi);
-                    uint32_t local = gi - (j ? C.s.incl[j - 1] : 0);
-                    x = base_elem(C, j, local, S.reuse);
-                    ok = check_elem(C, S, nb, j, x);
+            if (linear) {
+                // one leaf: survivors are only counted; two tiles per step
+                for (uint32_t t0 = 0; t0 < T; t0 += 128) {
+                    const uint32_t ga = t0 + lane, gb = t0 + 64 + lane;
+                    bool oka = ga < T, okb = gb < T;
+                    uint32_t ja = 0, xa = 0, jb = 0, xb = 0;
+                    if (oka) {
+                        ja = find_parent(C.s, np, ga);
+                        xa = base_elem(C, ja, ga - (ja ? C.s.incl[ja - 1] : 0), S.reuse);
+                    }
+                    if (okb) {
+                        jb = find_parent(C.s, np, gb);
+                        xb = base_elem(C, jb, gb - (jb ? C.s.incl[jb - 1] : 0), S.reuse);
+                    }
+                    check_pair(C, S, nb, ja, xa, oka, jb, xb, okb);
+                    lin += (unsigned long long)(__popcll(__ballot(oka)) + __popcll(__ballot(okb)));
                 }
-                if (linear) {
-                    lin += (unsigned long long)__popcll(__ballot(ok));
-                } else if (ok) {
-                    uint32_t mask = implied;
-                    for (uint32_t s2 = 0; s2 < nsig; s2++)
-                        if (((test >> s2) & 1u) && member_sig(C, P->sig[s2], j, x)) mask |= 1u << s2;
-                    if ((mask & below) == 0) atomicAdd(&C.s.hist[j * 16 + mask], 1u);
+            } else {
+                for (uint32_t t0 = 0; t0 < T; t0 += 64) {
+                    uint32_t gi = t0 + lane;
+                    bool ok = gi < T;
+                    uint32_t j = 0, x = 0;
+                    if (ok) {
+                        j = find_parent(C.s, np, gi);
+                        uint32_t local = gi - (j ? C.s.incl[j - 1] : 0);
+                        x = base_elem(C, j, local, S.reuse);
+                        ok = check_elem(C, S, nb, j, x);
+                    }
+                    if (ok) {
+                        uint32_t mask = implied;
+                        for (uint32_t s2 = 0; s2 < nsig; s2++)
+                            if (((test >> s2) & 1u) && member_sig(C, P->sig[s2], j, x)) mask |= 1u << s2;
+                        if ((mask & below) == 0) atomicAdd(&C.s.hist[j * 16 + mask], 1u);
+                    }
                 }
             }
             wave_sync();
@@ -545,11 +625,7 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
                 const uint32_t* A = (kind == 2) ? lvl_arrays(C.scr, a.cap, S.reuse).node + boff
                                                 : adj_of(a.g, kind) + boff;
                 const uint32_t* B = adj_of(a.g, S.cons_dir[pc]) + poff;
-                uint32_t ex[kMaxK];
-                uint32_t nex = 0;
-                for (uint32_t b = 0; b < nb; b++)
-                    if ((S.inj >> b) & 1u) ex[nex++] = uni(C.s.bound[b * 64 + j]);
-                lin += merge_count(C.s, A, blen, B, plen, ex, nex, lane);
+                lin += merge_count(C.s, A, blen, B, plen, S.inj, nb, j, lane);
             }
         }
         if (linear) {
@@ -636,14 +712,18 @@ __device__ void explore(Ctx& C, uint32_t n0) {
     }
 }
 
+#ifndef XM_MIN_BLOCKS_PER_CU
+#define XM_MIN_BLOCKS_PER_CU 8  // resident blocks per CU the register allocator must allow (8 waves per SIMD)
+#endif
+
 template <bool NONLIN>
-__global__ void __launch_bounds__(kBlockThreads) count_kernel(KArgs a) {
+__global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_kernel(KArgs a) {
     extern __shared__ uint32_t smem[];
     Ctx C;
     C.a = &a;
     C.lane = lane_id();
     const uint32_t wid = threadIdx.x >> 6;
-    C.s = carve(smem + wid * a.lds_words, a.maxc);
+    C.s = carve(smem + wid * a.lds_words, a.lds_rows, a.maxc, a.merge_min != 0xFFFFFFFFu);
     const uint64_t gw = (uint64_t)blockIdx.x * kWavesPerBlock + wid;
     C.scr = a.scratch + gw * (uint64_t)a.wave_words;
     C.acc_lo = C.acc_hi = 0;

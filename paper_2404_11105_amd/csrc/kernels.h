@@ -53,6 +53,7 @@ struct KArgs {
     const uint32_t* hubs;       // hub candidates for the split kernel (when roots == NULL)
     uint32_t n_hubs;
     uint32_t lds_words;         // LDS words per wave
+    uint32_t lds_rows;          // bound / ancestor rows (largest enumerated depth)
     uint32_t maxc;              // largest constraint count over plans and signatures
     uint32_t nonlinear;         // some plan counts a leaf group of several vertices
     uint32_t merge_min;         // cooperative merge thresholds
@@ -78,18 +79,23 @@ struct InitArgs {
 // First-level sub-range length for a root whose first-level list has L1
 // entries: the task size shrinks as the list grows, because each first-level
 // candidate of a long list usually carries a long list below it.
+constexpr uint32_t kMaxPieces = 4096;  // sub-range tasks per root and plan, at most
+
 __host__ __device__ inline uint32_t item_size(uint32_t L1, uint32_t split, uint32_t split_work) {
     uint32_t s = L1 ? split_work / L1 : split;
     s = s < split ? s : split;
-    return s < 1 ? 1 : s;
+    s = s < 1 ? 1 : s;
+    const uint32_t floor_s = (L1 + kMaxPieces - 1) / kMaxPieces;
+    return s > floor_s ? s : floor_s;
 }
 
-// LDS words per wave for a given largest constraint count and leaf mode.
-inline uint32_t lds_words_for(uint32_t maxc, bool nonlinear) {
-    return 2 * kMaxK * 64      // bound values, ancestor indices
+// LDS words per wave: `rows` bound levels (the largest enumerated depth of
+// the batch), the largest constraint count, and the optional parts.
+inline uint32_t lds_words_for(uint32_t rows, uint32_t maxc, bool nonlinear, bool merge) {
+    return 2 * rows * 64       // bound values, ancestor indices
            + 6 * 64            // base offset/length/kind, inclusive scan, segment counts, spare
            + 2 * maxc * 64     // check-list offset/length per constraint
-           + kMergeChunk       // merge chunk
+           + (merge ? kMergeChunk : 0)  // merge chunk
            + (nonlinear ? 16 * 64 : 0)  // leaf-group histograms
            + 32;               // wave state
 }

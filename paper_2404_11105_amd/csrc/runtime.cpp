@@ -25,6 +25,7 @@ struct xm_graph_s {
     uint32_t* hubs = nullptr;     // device, owned
     uint32_t n_hubs = 0;
     std::vector<uint32_t> hub_len;  // host: longest list of each hub (queue sizing)
+    std::vector<uint2> hub_deg;     // host: (out, in) degree of each hub
     uint32_t max_out = 0, max_in = 0;
     int n_cu = 0;
     size_t max_lds_block = 65536;
@@ -82,7 +83,7 @@ int plan_device_desc(xm_plan_t* p, int dev, const PlanDesc** out) {
 }
 
 struct Layout {
-    uint32_t chunk, split, split_work, cap, waves_per_cu, n_waves, n_blocks, e_max, maxc;
+    uint32_t chunk, split, split_work, cap, waves_per_cu, n_waves, n_blocks, e_max, maxc, merge_min;
     bool nonlinear;
     size_t off_ctl, off_flags, off_table, off_split, off_scratch, total;
     uint32_t split_cap, wave_words, lds_words;
@@ -90,15 +91,17 @@ struct Layout {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+constexpr uint64_t kMaxQueueBytes = 2ull << 30;  // split task queue, at most
+
 int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* plans,
                 const xm_count_opts* o, Layout& L) {
     if (!g) return fail(XM_ERR_INVALID, "graph is NULL");
     if (n_plans == 0 || !plans) return fail(XM_ERR_INVALID, "no plans");
     if (o && o->struct_size != 0 && o->struct_size < sizeof(xm_count_opts))
         return fail(XM_ERR_INVALID, "xm_count_opts.struct_size too small");
-    L.chunk = (o && o->chunk) ? o->chunk : 4;
+    L.chunk = (o && o->chunk) ? o->chunk : 1;
     L.split = (o && o->split) ? o->split : 64;
-    L.split_work = (o && o->split_work) ? o->split_work : 8192;
+    L.split_work = (o && o->split_work) ? o->split_work : 4096;
     L.cap = (o && o->cap) ? o->cap : 4096;
     L.waves_per_cu = (o && o->waves_per_cu) ? o->waves_per_cu : 0;  // 0: from occupancy
     if (L.chunk > 64) return fail(XM_ERR_INVALID, "chunk must be <= 64");
@@ -124,7 +127,8 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
         if (!D.linear) L.nonlinear = true;
         if (D.e >= 2) splittable++;
     }
-    L.lds_words = xm::lds_words_for(L.maxc, L.nonlinear);
+    L.merge_min = (o && o->merge_min) ? o->merge_min : xm::kMergeMin;
+    L.lds_words = xm::lds_words_for(L.e_max, L.maxc, L.nonlinear, L.merge_min != 0xFFFFFFFFu);
     if (L.waves_per_cu == 0) {
         // as many waves as can be resident at once: the kernel is persistent
         int bpc = xm::count_blocks_per_cu(L.nonlinear, (size_t)L.lds_words * 4 * xm::kWavesPerBlock);
@@ -133,23 +137,42 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
     L.n_waves = (uint32_t)g->n_cu * L.waves_per_cu;
     L.n_waves = (L.n_waves + xm::kWavesPerBlock - 1) / xm::kWavesPerBlock * xm::kWavesPerBlock;
     L.n_blocks = L.n_waves / xm::kWavesPerBlock;
-    L.lds_words = xm::lds_words_for(L.maxc, L.nonlinear);
     if ((size_t)L.lds_words * 4 * xm::kWavesPerBlock > g->max_lds_block)
         return fail(XM_ERR_INVALID, "plans need more LDS than a workgroup may use");
-    // split queue capacity: every splittable plan may split every hub root
+    // split task queue capacity
     uint64_t items = 0;
-    // pieces per root grow with the list length, so a hub's longest list bounds them
-    auto pieces = [&](uint32_t len) -> uint64_t {
-        uint32_t sz = xm::item_size(len, L.split, L.split_work);
+    // Exact count of sub-range tasks the split kernel will emit: per plan and
+    // hub, the root filter and the first-level list length (the shortest list
+    // of the level-1 constraints).  When the queue would pass kMaxQueueBytes
+    // the task size target split_work doubles for this launch.
+    auto pieces = [&](uint32_t len, uint32_t sw) -> uint64_t {
+        uint32_t sz = xm::item_size(len, L.split, sw);
         return len > sz ? (len + sz - 1) / sz : 0;
     };
-    if (o && o->roots_dev) {
-        items = (uint64_t)o->n_roots * pieces(max_list);
-    } else {
-        for (uint32_t h : g->hub_len) items += pieces(h);
+    auto count_items = [&](uint32_t sw) -> uint64_t {
+        uint64_t tot = 0;
+        if (o && o->roots_dev) {  // subset degrees are not known on the host: bound them
+            return (uint64_t)o->n_roots * pieces(max_list, sw) * splittable;
+        }
+        for (uint32_t i = 0; i < n_plans; i++) {
+            const PlanDesc& D = plans[i]->desc;
+            if (D.e < 2) continue;
+            for (size_t h = 0; h < g->hub_deg.size(); h++) {
+                uint2 d = g->hub_deg[h];
+                if (d.x < D.root_dout || d.y < D.root_din) continue;
+                uint32_t L1 = 0xFFFFFFFFu;
+                for (int c = 0; c < D.lvl[1].n_cons; c++) L1 = std::min(L1, D.lvl[1].cons_dir[c] ? d.y : d.x);
+                tot += pieces(L1, sw);
+            }
+        }
+        return tot;
+    };
+    items = count_items(L.split_work);
+    while (items * 16 > kMaxQueueBytes && L.split_work < (1u << 30)) {
+        L.split_work *= 2;
+        items = count_items(L.split_work);
     }
-    items *= splittable;
-    if (items > 0xFFFFFFF0ull) return fail(XM_ERR_INVALID, "split queue too large; raise split");
+    if (items > 0xFFFFFFF0ull) return fail(XM_ERR_INVALID, "split queue too large; raise split_work");
     L.split_cap = (uint32_t)std::max<uint64_t>(items, 1);
     L.wave_words = L.e_max * xm::kLvlArrays * L.cap;
     size_t off = 0;
@@ -199,8 +222,9 @@ int enqueue_count(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const*
     a.hubs = g->hubs;
     a.n_hubs = g->n_hubs;
     a.lds_words = L.lds_words;
+    a.lds_rows = L.e_max;
     a.maxc = L.maxc;
-    a.merge_min = (o && o->merge_min) ? o->merge_min : xm::kMergeMin;
+    a.merge_min = L.merge_min;
     a.merge_ratio = (o && o->merge_ratio) ? o->merge_ratio : xm::kMergeRatio;
     a.nonlinear = L.nonlinear ? 1u : 0u;
     a.wave_words = L.wave_words;
@@ -395,9 +419,11 @@ int xm_load_graph(uint32_t n, uint32_t m, const uint32_t* out_off, const uint32_
     std::sort(hubs.begin(), hubs.end(), [](auto& x, auto& y) { return x.first > y.first || (x.first == y.first && x.second < y.second); });
     g->n_hubs = (uint32_t)hubs.size();
     g->hub_len.resize(hubs.size());
+    g->hub_deg.resize(hubs.size());
     std::vector<uint32_t> hub_ids(std::max<size_t>(hubs.size(), 1), 0);
     for (size_t i = 0; i < hubs.size(); i++) {
         g->hub_len[i] = hubs[i].first;
+        g->hub_deg[i] = deg[hubs[i].second];
         hub_ids[i] = hubs[i].second;
     }
     g->stats.n = n;

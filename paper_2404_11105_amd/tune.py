@@ -24,13 +24,13 @@ import os
 import time
 
 SPACE = [
-    ("split_work", [4096, 8192, 16384, 65536]),
+    ("split_work", [4096, 16384, 65536]),
     ("split", [64, 128, 512]),
     ("chunk", [1, 4, 16]),
     ("waves_per_cu", [0, 16, 32]),
     ("merge_min", [0xFFFFFFFF, 64]),
 ]
-DEFAULTS = dict(split_work=8192, split=64, chunk=4, waves_per_cu=0, merge_min=0xFFFFFFFF)
+DEFAULTS = dict(split_work=4096, split=64, chunk=1, waves_per_cu=0, merge_min=0xFFFFFFFF)
 
 
 def signature(graph, plans) -> str:

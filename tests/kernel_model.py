@@ -44,7 +44,8 @@ class Model:
 
     def item_size(self, L1):
         s = self.split_work // L1 if L1 else self.split
-        return max(1, min(s, self.split))
+        s = max(1, min(s, self.split))
+        return max(s, -(-L1 // 4096))
 
     def deg(self, x):
         return self.out_off[x + 1] - self.out_off[x], self.in_off[x + 1] - self.in_off[x]

@@ -101,8 +101,8 @@ def test_rmat20_root_subset_parity(xa):
     g = xmgen.rmat(20, seed=0)
     assert g.m == gold["m"]
     G = xa.Graph(g)
-    roots = np.array(gold["roots"], dtype=np.uint32)
     for name, r in gold["results"].items():
+        roots = np.array(r["roots"], dtype=np.uint32)
         for reduced in (True, False):
             p = xa.Plan(xmgen.named(name), reduced=reduced, graph=G, root_vertex=r["root_vertex"])
             c = xa.Counter(G, [p], roots=roots)
