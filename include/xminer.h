@@ -176,8 +176,11 @@ typedef struct xm_count_opts {
     const uint32_t* roots_dev;
     uint32_t n_roots;
     uint32_t reserved0;
-    /* cancel flag: device int32; when it becomes nonzero, waves stop taking
-       new work and the status of unfinished plans is XM_ERR_CANCELLED. */
+    /* cancel flag: int32 the device can read (device memory, or pinned host
+       memory to raise it while the launch runs); each wave polls it on every
+       32nd task it takes and every 16 level windows of a task, and stops
+       once it is nonzero.  Every plan of
+       the launch then reports XM_ERR_CANCELLED and its count is partial. */
     const int32_t* cancel_dev;
     uint32_t split_work;    /* see split (default 4096, >= 4096) */
     /* single-leaf intersections whose two lists are both at least merge_min

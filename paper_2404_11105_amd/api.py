@@ -249,6 +249,51 @@ def plan_work(digraph, plan: Plan, roots=None, threads: int = 1, max_partial: in
                 exceeded=rc == 1)
 
 
+class Watchdog:
+    """A cancel flag in pinned host memory and a host timer that raises it.
+
+    Pass `flag` as Counter(cancel=...); `arm(seconds)` before a launch,
+    `disarm()` after it completed.  A launch that outlives the budget stops
+    at its next poll and reports XM_ERR_CANCELLED."""
+
+    def __init__(self):
+        import torch
+        self.flag = torch.zeros(1, dtype=torch.int32, pin_memory=True)
+        self._timer = None
+        # the device reads the flag through the mapped alias of the pinned page
+        hip = ctypes.CDLL("libamdhip64.so")
+        dptr = ctypes.c_void_p()
+        rc = hip.hipHostGetDevicePointer(ctypes.byref(dptr), ctypes.c_void_p(self.flag.data_ptr()), 0)
+        if rc != 0 or not dptr.value:
+            raise RuntimeError(f"pinned flag is not mapped for the device (hip error {rc})")
+        self._dev = dptr.value
+
+    def data_ptr(self) -> int:
+        """Device address of the flag (what the kernel polls)."""
+        return self._dev
+
+    def arm(self, seconds: float):
+        import threading
+        self.disarm()
+        self.flag[0] = 0
+        self._timer = threading.Timer(seconds, self._fire)
+        self._timer.daemon = True
+        self._timer.start()
+
+    def _fire(self):
+        self.flag[0] = 1
+
+    def disarm(self):
+        if self._timer is not None:
+            self._timer.cancel()
+            self._timer = None
+        self.flag[0] = 0
+
+    @property
+    def fired(self) -> bool:
+        return bool(self.flag[0].item())
+
+
 def workspace_bytes(graph: Graph, plans, **opts) -> int:
     """xm_workspace_size for these plans and options."""
     o = make_opts(**opts)

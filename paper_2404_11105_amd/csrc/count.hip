@@ -690,6 +690,7 @@ __device__ void explore(Ctx& C, uint32_t n0) {
     }
     wave_sync();
     uint32_t lv = 1;
+    uint32_t windows = 0;
     for (;;) {
         uint32_t nparents = uni(st[16 + lv - 1]);
         uint32_t cur = uni(st[lv]);
@@ -697,6 +698,15 @@ __device__ void explore(Ctx& C, uint32_t n0) {
             if (lv == 1) break;
             lv -= 1;
             continue;
+        }
+        // a long task still notices the cancel flag (counts are then partial)
+        if (C.a->cancel && (++windows & 15u) == 0) {
+            uint32_t stop = 0;
+            if (C.lane == 0) stop = __atomic_load_n(C.a->cancel, __ATOMIC_RELAXED) != 0;
+            if (uni(__shfl(stop, 0, 64))) {
+                if (C.lane == 0) atomicOr(&C.a->ctl[kCtlCancelled], 1u);
+                break;
+            }
         }
         uint32_t nout = expand(C, lv);
         if (lv == e - 1) {
@@ -732,12 +742,14 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
     const uint32_t chunks_per_plan = (a.n_src + a.chunk - 1) / a.chunk;
     const uint32_t total_chunks = chunks_per_plan * a.n_plans;
     Lvl F0 = lvl_arrays(C.scr, a.cap, 0);
+    uint32_t taken = 0;
     for (;;) {
         // ---- take a task
         uint32_t kind = 2, item = 0;
         if (C.lane == 0) {
             bool stop = false;
-            if (a.cancel && __atomic_load_n(a.cancel, __ATOMIC_RELAXED) != 0) {
+            // the flag may sit in host memory: poll it on every 32nd task only
+            if (a.cancel && (taken++ & 31u) == 0 && __atomic_load_n(a.cancel, __ATOMIC_RELAXED) != 0) {
                 atomicOr(&a.ctl[kCtlCancelled], 1u);
                 stop = true;
             }

@@ -15,6 +15,12 @@ timed with HIP events on the launch stream (one warm-up, then the median of
 `reps` launches), and the fastest value is kept.  Every configuration must
 return the same counts, else the tuner raises.  Results are cached in a
 JSON file keyed by the graph's size and the plans' descriptions.
+
+Each trial's first launch runs under a Watchdog: a candidate that has not
+finished within a few times the best time so far is cancelled on the device
+and counted as slower; the default configuration gets `first_budget_s`, and
+raises if it does not finish within it.  Timed repetitions reuse the
+launch that completed, so they run without the flag.
 """
 from __future__ import annotations
 
@@ -42,10 +48,24 @@ def signature(graph, plans) -> str:
     return h.hexdigest()[:24]
 
 
-def time_launch(graph, plans, stream, reps: int = 3, **opts):
-    """Median GPU milliseconds of one batched launch, and its counts."""
+def time_launch(graph, plans, stream, reps: int = 3, watchdog=None, budget_s: float = 0.0,
+                **opts):
+    """Median GPU milliseconds of one batched launch, and its counts.
+
+    With a watchdog, the first launch is cancelled after budget_s seconds;
+    then (inf, None) is returned."""
     import torch
     from .api import Counter
+    if watchdog is not None:
+        probe = Counter(graph, plans, cancel=watchdog, **opts)
+        watchdog.arm(budget_s)
+        probe.run(stream)
+        stream.synchronize()
+        watchdog.disarm()
+        counts, status = probe.results()
+        del probe
+        if any(s == -7 for s in status):
+            return float("inf"), None
     c = Counter(graph, plans, **opts)
     c.run(stream)
     stream.synchronize()
@@ -65,9 +85,10 @@ def time_launch(graph, plans, stream, reps: int = 3, **opts):
 
 
 def tune(graph, plans, stream=None, cache_path: str | None = None, reps: int = 3,
-         budget_s: float = 120.0, log=None):
+         budget_s: float = 120.0, log=None, first_budget_s: float = 60.0):
     """Best launch options for (graph, plans); returns (opts, record)."""
     import torch
+    from .api import Watchdog
     key = signature(graph, plans)
     cache = {}
     if cache_path and os.path.exists(cache_path):
@@ -77,14 +98,23 @@ def tune(graph, plans, stream=None, cache_path: str | None = None, reps: int = 3
     stream = stream or torch.cuda.Stream()
     t0 = time.time()
     best = dict(DEFAULTS)
-    best_ms, ref_counts = time_launch(graph, plans, stream, reps, **best)
+    wd = Watchdog()
+    best_ms, ref_counts = time_launch(graph, plans, stream, reps, wd, first_budget_s, **best)
+    if ref_counts is None:
+        raise RuntimeError(f"default launch did not finish within {first_budget_s} s")
     trials = [(dict(best), best_ms)]
     for name, values in SPACE:
         for v in values:
             if v == best[name] or time.time() - t0 > budget_s:
                 continue
             cand = dict(best, **{name: v})
-            ms, counts = time_launch(graph, plans, stream, reps, **cand)
+            ms, counts = time_launch(graph, plans, stream, reps, wd,
+                                     max(1.0, 4e-3 * best_ms), **cand)
+            if counts is None:
+                if log:
+                    log(f"[tune] {name}={v}: cancelled after {max(1.0, 4e-3 * best_ms):.1f} s")
+                trials.append((cand, ms))
+                continue
             if counts != ref_counts:
                 raise RuntimeError(f"counts changed with {cand}")
             trials.append((cand, ms))

@@ -109,3 +109,23 @@ def test_rmat20_root_subset_parity(xa):
             c.run()
             got, st = c.results()
             assert st == [0] and got == [int(r["count"])], (name, reduced)
+
+
+def test_watchdog_flag_in_pinned_host_memory(xa):
+    import time
+    banner("watchdog: pinned host cancel flag raised before the launch, then cleared")
+    g = xmgen.rmat(10, seed=2)
+    G = xa.Graph(g)
+    plans = [xa.Plan(xmgen.named(n), graph=G) for n in ["bifan", "c4"]]
+    wd = xa.Watchdog()
+    c = xa.Counter(G, plans, cancel=wd)
+    wd.arm(0.0)
+    time.sleep(0.05)
+    assert wd.fired
+    c.run()
+    counts, status = c.results()
+    assert status == [-7, -7]
+    wd.disarm()
+    c.run()
+    counts, status = c.results()
+    assert status == [0, 0] and counts == [oracle.count(g, p.pattern) for p in plans]
