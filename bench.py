@@ -302,6 +302,10 @@ def main():
     ap.add_argument("--split", type=int, default=0)
     ap.add_argument("--cap", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--row-min", type=int, default=None,
+                    help="shortest list with a dense membership row (default: the library's)")
+    ap.add_argument("--dense-rows", type=int, default=None,
+                    help="byte budget of the dense rows (0: none; default: the library's)")
     ap.add_argument("--workload", default="rmat16", choices=["rmat16", "batch256", "serve"],
                     help="rmat16: the contract line (default); batch256 / serve: the batched "
                          "and serving workloads, each printing its own JSON line")
@@ -335,7 +339,7 @@ def main():
     log("[bench] generating R-MAT scale 16")
     g = xmgen.rmat(16, seed=0)
     pats = [xmgen.named(n) for n in PATTERNS]
-    G = Graph(g)
+    G = Graph(g, dense_rows=args.dense_rows, row_min=args.row_min)
     tune = dict(chunk=args.chunk, split=args.split, cap=args.cap, waves_per_cu=args.waves_per_cu)
     red = [Plan(p, reduced=True, graph=G) for p in pats]
     unred = [Plan(p, reduced=False, graph=G) for p in pats]
@@ -407,7 +411,7 @@ def main():
                    "graph": "R-MAT scale 16, edge factor 16, (.57,.19,.19,.05), seed 0",
                    "n": g.n, "m": g.m, "patterns": PATTERNS, "plan": "reduced",
                    "launch": "one persistent launch for 4 patterns, HIP graph replay",
-                   "parallelism": "1 GPU"},
+                   "parallelism": "1 GPU", "dense_rows": G.dense_rows_info()},
         "counts": [str(c) for c in counts],
         "counts_match_oracle": gold_ok,
         "kernel_ms": round(kern_ms, 4),

@@ -86,7 +86,32 @@ int xm_load_graph(uint32_t n, uint32_t m,
                   const uint32_t* out_off, const uint32_t* out_adj,
                   const uint32_t* in_off, const uint32_t* in_adj,
                   uint32_t flags, void* hip_stream, xm_graph_t** out);
+/* Frees the graph; fails with XM_ERR_INVALID while captured launches
+ * (xm_exec_t) of it exist. */
 int xm_free_graph(xm_graph_t* g);
+/* Dense membership rows for long adjacency lists.
+ *
+ * Every candidate test of Algorithm 2 asks whether a node x lies in the out-
+ * or in-list of a bound node (the set intersections that build candidate
+ * sets).  For lists of at least min_len elements this call stores an n-bit
+ * row per list (bit x set iff x is in the list) in device memory the library
+ * owns, and xm_count then answers such a test with one load instead of a
+ * search of the sorted list.  Counts do not change.
+ *
+ * max_bytes bounds the rows' total size: the threshold starts at
+ * max(min_len, 32) and doubles until all rows of lists at least that long,
+ * in both directions, fit.  *out_min_len (nullable) receives the threshold
+ * used, 0 if no row was built.  max_bytes = 0 removes the rows.  Graphs with
+ * n >= 2^31 get no rows.  The call synchronises the device (launches in
+ * flight may read the old rows) and fails with XM_ERR_INVALID while captured
+ * launches (xm_exec_t) of this graph exist.  Rows cost ceil(n/32)*4 bytes
+ * each; XM_ERR_OOM leaves the graph without rows. */
+int xm_graph_dense_rows(xm_graph_t* g, uint64_t max_bytes, uint32_t min_len, void* hip_stream,
+                        uint32_t* out_min_len);
+/* Current rows: threshold (0 = none), rows per direction, bytes. */
+int xm_graph_dense_rows_info(const xm_graph_t* g, uint32_t* min_len, uint32_t* n_out_rows,
+                             uint32_t* n_in_rows, uint64_t* bytes);
+
 /* Graph facts: n, m, max out-degree, max in-degree (any pointer may be NULL). */
 int xm_graph_info(const xm_graph_t* g, uint32_t* n, uint32_t* m,
                   uint32_t* max_out, uint32_t* max_in);

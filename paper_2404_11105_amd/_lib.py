@@ -60,7 +60,8 @@ class XminerError(RuntimeError):
 
 
 EXPORTS = [
-    "xm_load_graph", "xm_free_graph", "xm_graph_info", "xm_plan", "xm_plan_describe",
+    "xm_load_graph", "xm_free_graph", "xm_graph_info", "xm_graph_dense_rows", "xm_graph_dense_rows_info",
+    "xm_plan", "xm_plan_describe",
     "xm_plan_root_vertex", "xm_free_plan", "xm_plan_work", "xm_workspace_size", "xm_count", "xm_count_capture",
     "xm_exec_launch", "xm_free_exec", "xm_strerror", "xm_last_error", "xm_version",
 ]
@@ -80,6 +81,8 @@ def lib():
         L.xm_load_graph.argtypes = [U32, U32, P, P, P, P, U32, P, ctypes.POINTER(P)]
         L.xm_free_graph.argtypes = [P]
         L.xm_graph_info.argtypes = [P, P, P, P, P]
+        L.xm_graph_dense_rows.argtypes = [P, ctypes.c_uint64, U32, P, P]
+        L.xm_graph_dense_rows_info.argtypes = [P, P, P, P, P]
         L.xm_plan.argtypes = [U32, U32, P, U32, P, ctypes.POINTER(P)]
         L.xm_plan_describe.argtypes = [P, ctypes.c_char_p, SZ, ctypes.POINTER(SZ)]
         L.xm_plan_root_vertex.argtypes = [P]
@@ -95,7 +98,8 @@ def lib():
         L.xm_strerror.restype = ctypes.c_char_p
         L.xm_last_error.restype = ctypes.c_char_p
         L.xm_version.restype = ctypes.c_char_p
-        for name in ["xm_load_graph", "xm_free_graph", "xm_graph_info", "xm_plan",
+        for name in ["xm_load_graph", "xm_free_graph", "xm_graph_info", "xm_graph_dense_rows",
+                     "xm_graph_dense_rows_info", "xm_plan",
                      "xm_plan_describe", "xm_plan_root_vertex", "xm_free_plan", "xm_plan_work",
                      "xm_count",
                      "xm_count_capture", "xm_exec_launch", "xm_free_exec"]:

@@ -34,10 +34,16 @@ class Graph:
     """A resident data graph: uint32 out-CSR + in-CSR in device memory.
 
     The device tensors are owned here and borrowed by the library
-    (XM_MEM_DEVICE) until close().
+    (XM_MEM_DEVICE) until close().  Lists of at least `row_min` elements get
+    dense membership rows (xm_graph_dense_rows) within `dense_rows` bytes;
+    dense_rows=0 keeps every membership test a sorted-list search.
     """
 
-    def __init__(self, digraph, device: str = "cuda", validate: bool = False, stream=None):
+    DEFAULT_ROW_BYTES = 2 << 30
+    DEFAULT_ROW_MIN = 32
+
+    def __init__(self, digraph, device: str = "cuda", validate: bool = False, stream=None,
+                 dense_rows: int | None = None, row_min: int | None = None):
         import torch
         self.n = int(digraph.n)
         self.m = int(digraph.m)
@@ -55,6 +61,23 @@ class Graph:
             check(lib().xm_load_graph(self.n, self.m, *[ctypes.c_void_p(t.data_ptr()) for t in self.tensors],
                                       flags, _stream_ptr(stream), ctypes.byref(h)))
         self.handle = h
+        self.set_dense_rows(self.DEFAULT_ROW_BYTES if dense_rows is None else dense_rows,
+                            self.DEFAULT_ROW_MIN if row_min is None else row_min, stream)
+
+    def set_dense_rows(self, max_bytes: int, row_min: int = 32, stream=None) -> int:
+        """(Re)build dense rows within max_bytes; returns the threshold used (0: none)."""
+        import torch
+        t = ctypes.c_uint32()
+        with torch.cuda.device(self.device):
+            check(lib().xm_graph_dense_rows(self.handle, int(max_bytes), int(row_min), _stream_ptr(stream),
+                                            ctypes.byref(t)))
+        return t.value
+
+    def dense_rows_info(self) -> dict:
+        t, no, ni, b = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint64()
+        check(lib().xm_graph_dense_rows_info(self.handle, ctypes.byref(t), ctypes.byref(no), ctypes.byref(ni),
+                                             ctypes.byref(b)))
+        return {"row_min": t.value, "out_rows": no.value, "in_rows": ni.value, "bytes": b.value}
 
     def info(self):
         n, m, mo, mi = (ctypes.c_uint32() for _ in range(4))

@@ -11,7 +11,10 @@
 //
 // Per element of a base list a lane checks, in order: injectivity against
 // the bound nodes (visited marks), the degree thresholds, and membership in
-// every other constraint list (sorted uint32 lists, binary search).  The
+// every other constraint list: one bit test when the list is long enough to
+// have a dense row (an n-bit membership row built at graph load, the HBM
+// analogue of staging a hub's list), else a binary search of the sorted
+// uint32 list.  The
 // survivors are compacted with a 64-bit ballot and a popcount.  The leaf
 // group of a plan is counted, not enumerated: with one leaf the count is a
 // popcount sum; with several, each partial match builds a membership
@@ -72,6 +75,25 @@ __device__ __forceinline__ const uint32_t* adj_of(const DevGraph& g, uint32_t di
 }
 __device__ __forceinline__ const uint32_t* off_of(const DevGraph& g, uint32_t dir) {
     return dir ? g.in_off : g.out_off;
+}
+
+// Membership of x in the list that owns dense row r of direction dir.
+__device__ __forceinline__ bool row_has(const DevGraph& g, uint32_t dir, uint32_t r, uint32_t x) {
+    const uint32_t* row = (dir ? g.rows_in : g.rows_out) + (uint64_t)r * g.row_words;
+    return (row[x >> 5] >> (x & 31u)) & 1u;
+}
+
+// A probe list (offset o, length l) of node nd becomes a row reference
+// (o = row, l = kRowLen) when the list is long enough to have a row.
+__device__ __forceinline__ void to_row(const DevGraph& g, uint32_t dir, uint32_t nd, uint32_t& o, uint32_t& l) {
+    if (l != kSkip && l >= g.row_min) {
+        const uint2 r = g.row_of[nd];
+        const uint32_t row = dir ? r.y : r.x;
+        if (row != kSkip) {
+            o = row;
+            l = kRowLen;
+        }
+    }
 }
 
 // Unsigned 128-bit add into (lo, hi) with an overflow flag.
@@ -202,6 +224,7 @@ __device__ uint32_t phase_a(Ctx& C, const LevelDesc& D, uint32_t lv, uint32_t p,
                     const uint32_t* off = off_of(g, D.cons_dir[c]);
                     o = off[nd];
                     l = off[nd + 1] - o;
+                    to_row(g, D.cons_dir[c], nd, o, l);
                 }
                 C.s.chk_off[c * 64 + lane] = o;
                 C.s.chk_len[c * 64 + lane] = l;
@@ -225,6 +248,14 @@ __device__ uint32_t phase_a(Ctx& C, const LevelDesc& D, uint32_t lv, uint32_t p,
             }
         }
         C.s.chk_len[bc * 64 + lane] = kSkip;
+        // long probe lists are tested in their dense rows
+        for (uint32_t c = 0; c < D.n_cons; c++) {
+            uint32_t o = C.s.chk_off[c * 64 + lane], l = C.s.chk_len[c * 64 + lane];
+            if (c == bc || l < g.row_min) continue;
+            to_row(g, D.cons_dir[c], C.s.bound[D.cons_lvl[c] * 64 + lane], o, l);
+            C.s.chk_off[c * 64 + lane] = o;
+            C.s.chk_len[c * 64 + lane] = l;
+        }
         C.s.base_kind[lane] = D.cons_dir[bc];
         C.s.base_off[lane] = bo;
         len = best;
@@ -300,7 +331,10 @@ __device__ __forceinline__ bool check_elem(const Ctx& C, const LevelDesc& D, uin
     }
     for (uint32_t c = 0; c < D.n_cons && ok; c++) {
         uint32_t l = C.s.chk_len[c * 64 + j];
-        if (l != kSkip) ok = contains(adj_of(g, D.cons_dir[c]) + C.s.chk_off[c * 64 + j], l, x);
+        if (l == kRowLen)
+            ok = row_has(g, D.cons_dir[c], C.s.chk_off[c * 64 + j], x);
+        else if (l != kSkip)
+            ok = contains(adj_of(g, D.cons_dir[c]) + C.s.chk_off[c * 64 + j], l, x);
     }
     return ok;
 }
@@ -323,12 +357,18 @@ __device__ __forceinline__ void check_pair(const Ctx& C, const LevelDesc& D, uin
     }
     for (uint32_t c = 0; c < D.n_cons; c++) {
         const uint32_t lA = C.s.chk_len[c * 64 + ja], lB = C.s.chk_len[c * 64 + jb];
-        bool fa = oka && lA != kSkip, fb = okb && lB != kSkip;
+        const uint32_t oA = C.s.chk_off[c * 64 + ja], oB = C.s.chk_off[c * 64 + jb];
+        const uint32_t dir = D.cons_dir[c];
+        // dense rows: one bit test each
+        if (oka && lA == kRowLen) oka = row_has(g, dir, oA, xa);
+        if (okb && lB == kRowLen) okb = row_has(g, dir, oB, xb);
+        bool fa = oka && lA != kSkip && lA != kRowLen, fb = okb && lB != kSkip && lB != kRowLen;
         if (!(fa || fb)) continue;
-        const uint32_t* adj = adj_of(g, D.cons_dir[c]);
-        contains2(adj + C.s.chk_off[c * 64 + ja], lA, xa, fa, adj + C.s.chk_off[c * 64 + jb], lB, xb, fb);
-        if (oka && lA != kSkip) oka = fa;
-        if (okb && lB != kSkip) okb = fb;
+        const uint32_t* adj = adj_of(g, dir);
+        const bool sa = fa, sb = fb;
+        contains2(adj + oA, lA, xa, fa, adj + oB, lB, xb, fb);
+        if (sa) oka = fa;
+        if (sb) okb = fb;
     }
 }
 
@@ -341,7 +381,9 @@ __device__ __forceinline__ bool member_sig(const Ctx& C, const LevelDesc& S, uin
         uint32_t nd = C.s.bound[S.cons_lvl[c] * 64 + j];
         const uint32_t* off = off_of(g, S.cons_dir[c]);
         uint32_t o = off[nd];
-        ok = contains(adj_of(g, S.cons_dir[c]) + o, off[nd + 1] - o, x);
+        uint32_t l = off[nd + 1] - o;
+        to_row(g, S.cons_dir[c], nd, o, l);
+        ok = (l == kRowLen) ? row_has(g, S.cons_dir[c], o, x) : contains(adj_of(g, S.cons_dir[c]) + o, l, x);
     }
     return ok;
 }
@@ -556,7 +598,7 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
                         probe_c = c;
                         nprobe++;
                     }
-                if (nprobe == 1) {
+                if (nprobe == 1 && C.s.chk_len[probe_c * 64 + lane] != kRowLen) {
                     uint32_t pl = C.s.chk_len[probe_c * 64 + lane];
                     uint32_t mn = len < pl ? len : pl, mx = len < pl ? pl : len;
                     big = mn >= a.merge_min && (uint64_t)mx <= (uint64_t)a.merge_ratio * mn;
@@ -887,6 +929,30 @@ int count_blocks_per_cu(bool nonlin, size_t lds_bytes) {
     else
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, count_kernel<false>, kBlockThreads, lds_bytes);
     return e == hipSuccess ? nb : 0;
+}
+
+// One block per dense row: set the bit of every list element.
+__global__ void rows_kernel(DevGraph g, const uint32_t* row_node, uint32_t n_out_rows, uint32_t n_rows,
+                            uint32_t* rows) {
+    for (uint32_t r = blockIdx.x; r < n_rows; r += gridDim.x) {
+        const uint32_t dir = r >= n_out_rows ? 1u : 0u;
+        const uint32_t v = row_node[r];
+        const uint32_t* off = off_of(g, dir);
+        const uint32_t* adj = adj_of(g, dir);
+        uint32_t* row = rows + (uint64_t)r * g.row_words;
+        for (uint32_t i = off[v] + threadIdx.x; i < off[v + 1]; i += blockDim.x) {
+            const uint32_t x = adj[i];
+            atomicOr(&row[x >> 5], 1u << (x & 31u));
+        }
+    }
+}
+
+hipError_t build_rows(const DevGraph& g, const uint32_t* row_node, uint32_t n_out_rows, uint32_t n_rows,
+                      uint32_t* rows, hipStream_t stream) {
+    if (n_rows == 0) return hipSuccess;
+    uint32_t blocks = n_rows < 65535u ? n_rows : 65535u;
+    hipLaunchKernelGGL(rows_kernel, dim3(blocks), dim3(256), 0, stream, g, row_node, n_out_rows, n_rows, rows);
+    return hipGetLastError();
 }
 
 hipError_t launch_count(const InitArgs* inits, int n_inits, const KArgs& a, uint32_t n_blocks,

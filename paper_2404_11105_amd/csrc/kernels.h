@@ -33,8 +33,22 @@ struct DevGraph {
     const uint32_t* in_adj;
     const uint2* deg;   // (out-degree, in-degree)
     uint32_t n;
-    uint32_t pad;
+    uint32_t row_min;   // lists at least this long have a dense row (kNoRows: none)
+    // dense membership rows of long lists: row r of a direction is row_words
+    // uint32 words, bit x set iff node x is in the list
+    const uint32_t* rows_out;
+    const uint32_t* rows_in;
+    const uint2* row_of;  // per node: (out row, in row), 0xFFFFFFFF = no row
+    uint64_t row_words;
 };
+
+constexpr uint32_t kNoRows = 0xFFFFFFFFu;
+constexpr uint32_t kRowLen = 0xFFFFFFFEu;  // probe-list length marker: test a dense row
+
+// Set the bits of dense rows [0, n_rows): row r holds the out-list (r <
+// n_out_rows) or in-list of node row_node[r].  Rows must be zeroed first.
+hipError_t build_rows(const DevGraph& g, const uint32_t* row_node, uint32_t n_out_rows, uint32_t n_rows,
+                      uint32_t* rows, hipStream_t stream);
 
 struct KArgs {
     DevGraph g;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -27,6 +28,13 @@ struct xm_graph_s {
     std::vector<uint32_t> hub_len;  // host: longest list of each hub (queue sizing)
     std::vector<uint2> hub_deg;     // host: (out, in) degree of each hub
     uint32_t max_out = 0, max_in = 0;
+    std::vector<uint2> hdeg;        // host: (out, in) degree per node
+    // dense membership rows of long lists (xm_graph_dense_rows)
+    uint32_t* rows = nullptr;       // device, owned: out rows, then in rows
+    uint2* row_of = nullptr;        // device, owned: per node (out row, in row)
+    uint32_t row_min = xm::kNoRows, n_rows_out = 0, n_rows_in = 0;
+    uint64_t row_words = 0;
+    mutable std::atomic<int> execs{0};  // captured launches that hold this graph's pointers
     int n_cu = 0;
     size_t max_lds_block = 65536;
     xm::GraphStats stats;
@@ -40,6 +48,7 @@ struct xm_plan_s {
 };
 
 struct xm_exec_s {
+    const xm_graph_s* g = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -206,7 +215,17 @@ int enqueue_count(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const*
     char* base = static_cast<char*>(ws);
     xm::KArgs a;
     std::memset(&a, 0, sizeof(a));
-    a.g = {g->out_off, g->out_adj, g->in_off, g->in_adj, g->deg, g->n, 0};
+    a.g.out_off = g->out_off;
+    a.g.out_adj = g->out_adj;
+    a.g.in_off = g->in_off;
+    a.g.in_adj = g->in_adj;
+    a.g.deg = g->deg;
+    a.g.n = g->n;
+    a.g.row_min = g->rows ? g->row_min : xm::kNoRows;
+    a.g.rows_out = g->rows;
+    a.g.rows_in = g->rows ? g->rows + (uint64_t)g->n_rows_out * g->row_words : nullptr;
+    a.g.row_of = g->row_of;
+    a.g.row_words = g->row_words;
     a.plans = reinterpret_cast<const PlanDesc*>(base + L.off_table);
     a.n_plans = n_plans;
     a.chunk = L.chunk;
@@ -432,6 +451,7 @@ int xm_load_graph(uint32_t n, uint32_t m, const uint32_t* out_off, const uint32_
         g->stats.frac_out_ge[t] = (double)ge_out[t] / n;
         g->stats.frac_in_ge[t] = (double)ge_in[t] / n;
     }
+    g->hdeg = deg;
     if ((e = hipMalloc(&g->deg, (size_t)n * sizeof(uint2))) != hipSuccess ||
         (e = hipMalloc(&g->hubs, hub_ids.size() * 4)) != hipSuccess) {
         cleanup();
@@ -467,6 +487,7 @@ int xm_plan_work(uint32_t n, const uint32_t* out_off, const uint32_t* out_adj, c
 
 int xm_free_graph(xm_graph_t* g) {
     if (!g) return XM_OK;
+    if (g->execs.load() != 0) return fail(XM_ERR_INVALID, "graph has captured launches; free them first");
     if (g->owns_csr) {
         (void)hipFree((void*)g->out_off);
         (void)hipFree((void*)g->out_adj);
@@ -475,7 +496,112 @@ int xm_free_graph(xm_graph_t* g) {
     }
     if (g->deg) (void)hipFree(g->deg);
     if (g->hubs) (void)hipFree(g->hubs);
+    if (g->rows) (void)hipFree(g->rows);
+    if (g->row_of) (void)hipFree(g->row_of);
     delete g;
+    return XM_OK;
+}
+
+int xm_graph_dense_rows(xm_graph_t* g, uint64_t max_bytes, uint32_t min_len, void* hip_stream,
+                        uint32_t* out_min_len) {
+    if (!g) return fail(XM_ERR_INVALID, "graph is NULL");
+    if (out_min_len) *out_min_len = 0;
+    if (g->execs.load() != 0) return fail(XM_ERR_INVALID, "graph has captured launches; free them first");
+    int cur_dev = 0;
+    HIP_TRY(hipGetDevice(&cur_dev), "hipGetDevice");
+    if (cur_dev != g->device) return fail(XM_ERR_INVALID, "current device differs from the graph's");
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    // launches in flight may read the old rows
+    HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (g->rows) (void)hipFree(g->rows);
+    if (g->row_of) (void)hipFree(g->row_of);
+    g->rows = nullptr;
+    g->row_of = nullptr;
+    g->row_min = xm::kNoRows;
+    g->n_rows_out = g->n_rows_in = 0;
+    g->row_words = 0;
+    if (max_bytes == 0 || g->n >= 0x80000000u) return XM_OK;
+    const uint64_t words = ((uint64_t)g->n + 31) / 32;
+    const uint64_t row_bytes = words * 4;
+    // the smallest threshold (doubling from min_len, at least 32) whose rows fit
+    uint64_t t = std::max<uint32_t>(min_len, 32);
+    const uint32_t longest = std::max(g->max_out, g->max_in);
+    uint64_t n_out = 0, n_in = 0;
+    for (; t <= longest; t *= 2) {
+        n_out = n_in = 0;
+        for (const uint2& d : g->hdeg) {
+            n_out += d.x >= t;
+            n_in += d.y >= t;
+        }
+        if ((n_out + n_in) * row_bytes <= max_bytes) break;
+    }
+    if (t > longest || n_out + n_in == 0) return XM_OK;
+    std::vector<uint2> row_of(g->n, make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu));
+    std::vector<uint32_t> row_node;
+    row_node.reserve(n_out + n_in);
+    for (uint32_t v = 0; v < g->n; v++)
+        if (g->hdeg[v].x >= t) {
+            row_of[v].x = (uint32_t)row_node.size();
+            row_node.push_back(v);
+        }
+    for (uint32_t v = 0; v < g->n; v++)
+        if (g->hdeg[v].y >= t) {
+            row_of[v].y = (uint32_t)(row_node.size() - n_out);
+            row_node.push_back(v);
+        }
+    uint32_t* rn = nullptr;
+    hipError_t e;
+    if ((e = hipMalloc(&g->rows, (n_out + n_in) * row_bytes)) != hipSuccess ||
+        (e = hipMalloc(&g->row_of, (size_t)g->n * sizeof(uint2))) != hipSuccess ||
+        (e = hipMalloc(&rn, row_node.size() * 4)) != hipSuccess) {
+        if (g->rows) (void)hipFree(g->rows);
+        if (g->row_of) (void)hipFree(g->row_of);
+        g->rows = nullptr;
+        g->row_of = nullptr;
+        return fail(XM_ERR_OOM, "hipMalloc(dense rows)");
+    }
+    g->row_words = words;
+    g->n_rows_out = (uint32_t)n_out;
+    g->n_rows_in = (uint32_t)n_in;
+    g->row_min = (uint32_t)t;
+    xm::DevGraph dg{};
+    dg.out_off = g->out_off;
+    dg.out_adj = g->out_adj;
+    dg.in_off = g->in_off;
+    dg.in_adj = g->in_adj;
+    dg.n = g->n;
+    dg.row_words = words;
+    if ((e = hipMemsetAsync(g->rows, 0, (n_out + n_in) * row_bytes, stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(g->row_of, row_of.data(), (size_t)g->n * sizeof(uint2), hipMemcpyHostToDevice,
+                            stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(rn, row_node.data(), row_node.size() * 4, hipMemcpyHostToDevice, stream)) !=
+            hipSuccess ||
+        (e = xm::build_rows(dg, rn, (uint32_t)n_out, (uint32_t)(n_out + n_in), g->rows, stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(stream)) != hipSuccess) {
+        (void)hipStreamSynchronize(stream);
+        (void)hipFree(rn);
+        (void)hipFree(g->rows);
+        (void)hipFree(g->row_of);
+        g->rows = nullptr;
+        g->row_of = nullptr;
+        g->row_min = xm::kNoRows;
+        g->n_rows_out = g->n_rows_in = 0;
+        g->row_words = 0;
+        return hip_fail(e, "build dense rows");
+    }
+    (void)hipFree(rn);
+    if (out_min_len) *out_min_len = (uint32_t)t;
+    return XM_OK;
+}
+
+int xm_graph_dense_rows_info(const xm_graph_t* g, uint32_t* min_len, uint32_t* n_out_rows, uint32_t* n_in_rows,
+                             uint64_t* bytes) {
+    if (!g) return fail(XM_ERR_INVALID, "graph is NULL");
+    const bool on = g->rows != nullptr;
+    if (min_len) *min_len = on ? g->row_min : 0;
+    if (n_out_rows) *n_out_rows = on ? g->n_rows_out : 0;
+    if (n_in_rows) *n_in_rows = on ? g->n_rows_in : 0;
+    if (bytes) *bytes = on ? (uint64_t)(g->n_rows_out + g->n_rows_in) * g->row_words * 4 : 0;
     return XM_OK;
 }
 
@@ -587,6 +713,8 @@ int xm_count_capture(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* con
         delete x;
         return hip_fail(e, "hipGraphInstantiate");
     }
+    x->g = g;
+    g->execs.fetch_add(1);
     *out = x;
     return XM_OK;
 }
@@ -601,6 +729,7 @@ int xm_free_exec(xm_exec_t* x) {
     if (!x) return XM_OK;
     if (x->exec) (void)hipGraphExecDestroy(x->exec);
     if (x->graph) (void)hipGraphDestroy(x->graph);
+    if (x->g) x->g->execs.fetch_sub(1);
     delete x;
     return XM_OK;
 }

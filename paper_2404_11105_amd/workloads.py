@@ -4,13 +4,14 @@ batch256: 256 seeded random connected patterns of 3-6 vertices (xmgen's
 random_pattern recipe) counted against one resident R-MAT scale 22 graph.
 Random sparse patterns on a graph with ~10^5-degree hubs can have 10^15 or
 more partial matches, which no launch can enumerate, so candidates pass a
-work cap: the plan's algorithmic work (xm_plan_work) on the 16 largest hubs
-plus a seeded uniform sample of 256 roots, extrapolated to all roots, must
-stay under CAP_ELEMENTS and neither walk may pass WALK_BUDGET partial
-matches.  Sizes are drawn round-robin (3, 4, 5, 6) with a quota of 64 each;
-a size whose candidates run out (MAX_DRAWS) is backfilled by smaller sizes.
-The accepted seeds are stored in workloads/batch256.json with the counts of
-rejected draws.
+work cap: the plan's algorithmic work (xm_plan_work) is estimated from roots
+sampled by degree rank -- all of the 16 largest, then 16 seeded roots from
+each rank stratum [16,64), [64,256), ..., [262144, n), each weighted by its
+stratum size -- and must stay under CAP_ELEMENTS, with no walk passing
+WALK_BUDGET partial matches.  Sizes are drawn round-robin (3, 4, 5, 6) with a
+quota of 64 each; a size whose candidates run out (MAX_DRAWS) is backfilled
+by smaller sizes.  The accepted seeds are stored in workloads/batch256.json
+with the counts of rejected draws.
 
     python -m paper_2404_11105_amd.workloads batch256
 """
@@ -25,9 +26,10 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 BATCH_PATH = os.path.join(HERE, "workloads", "batch256.json")
-CAP_ELEMENTS = 2e10
+CAP_ELEMENTS = 5e9
 WALK_BUDGET = 2_000_000
-MAX_DRAWS = 250
+STRATA = [0, 16, 64, 256, 1024, 4096, 16384, 65536, 262144]
+MAX_DRAWS = 1000
 SEED_BASE = {3: 300000, 4: 400000, 5: 500000, 6: 600000}
 
 
@@ -49,8 +51,16 @@ def select_batch(threads: int = 8):
     t0 = time.time()
     g = batch_graph()
     deg = np.maximum(g.out_deg(), g.in_deg())
-    hubs = np.argsort(-deg, kind="stable")[:16].astype(np.uint32)
-    sample = np.sort(np.random.default_rng(22).choice(g.n, 256, replace=False)).astype(np.uint32)
+    order = np.argsort(-deg, kind="stable").astype(np.uint32)
+    rng = np.random.default_rng(22)
+    strata = []  # (roots, weight)
+    bounds = STRATA + [g.n]
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        idx = order[a:b]
+        if b - a <= 16:
+            strata.append((np.sort(idx), 1.0))
+        else:
+            strata.append((np.sort(rng.choice(idx, size=16, replace=False)), (b - a) / 16.0))
     quota = {3: 64, 4: 64, 5: 64, 6: 64}
     accepted, rejected, draws, est = [], {k: 0 for k in quota}, {k: 0 for k in quota}, []
     exhausted = set()
@@ -67,10 +77,14 @@ def select_batch(threads: int = 8):
             progressed = True
             p = xmgen.random_pattern(k, seed)
             plan = Plan(p, True)
-            wh = plan_work(g, plan, roots=hubs, threads=threads, max_partial=WALK_BUDGET)
-            ws = plan_work(g, plan, roots=sample, threads=threads, max_partial=WALK_BUDGET)
-            e = wh["elements"] + ws["elements"] * (g.n - hubs.size) / sample.size
-            if wh["exceeded"] or ws["exceeded"] or e > CAP_ELEMENTS:
+            e, exceeded = 0.0, False
+            for roots, w in strata:
+                r = plan_work(g, plan, roots=roots, threads=threads, max_partial=WALK_BUDGET)
+                e += r["elements"] * w
+                if r["exceeded"] or e > CAP_ELEMENTS:
+                    exceeded = True
+                    break
+            if exceeded:
                 rejected[k] += 1
                 continue
             accepted.append((k, seed))
@@ -89,7 +103,7 @@ def select_batch(threads: int = 8):
             else:
                 break
     rec = {"graph": "rmat(scale=22, edge_factor=16, abcd=(.57,.19,.19,.05), seed=0)",
-           "recipe": "random_pattern(k, seed); work cap on hubs + uniform root sample",
+           "recipe": "random_pattern(k, seed); work cap from a degree-stratified root sample",
            "cap_elements": CAP_ELEMENTS, "walk_budget": WALK_BUDGET,
            "accepted": accepted, "estimated_elements": est,
            "rejected_per_k": rejected, "draws_per_k": draws,

@@ -83,6 +83,27 @@ def test_tunings_exercise_splits_and_partial_windows(xa, tune):
             assert run(xa, g, [p], G=G, reduced=reduced, **tune) == [w]
 
 
+@pytest.mark.parametrize("rows", [dict(dense_rows=0), dict(row_min=64, dense_rows=1 << 20),
+                                  dict(row_min=32, dense_rows=40 * 256)])
+def test_dense_rows_do_not_change_counts(xa, rows):
+    banner(f"rmat 11 named patterns with dense rows {rows}")
+    _, g, pats, want = golden_case("rmat11_named")
+    G = xa.Graph(g, **rows)
+    info = G.dense_rows_info()
+    t = info["row_min"]
+    if rows["dense_rows"] == 0:
+        assert t == 0 and info["bytes"] == 0
+    else:
+        # every list at least t long has a row, within the byte budget
+        assert t >= rows["row_min"]
+        n_out = int((np.diff(g.out_off.astype(np.int64)) >= t).sum())
+        n_in = int((np.diff(g.in_off.astype(np.int64)) >= t).sum())
+        assert (info["out_rows"], info["in_rows"]) == (n_out, n_in) and n_out + n_in > 0
+        assert info["bytes"] == (n_out + n_in) * ((g.n + 31) // 32) * 4 <= rows["dense_rows"]
+    for reduced in (True, False):
+        assert run(xa, g, pats, G=G, reduced=reduced) == want
+
+
 def test_batched_equals_plain(xa):
     banner("batched vs plain, 24 random patterns on rmat 10")
     _, g, pats, want = golden_case("batch_rmat10")
