@@ -101,8 +101,9 @@ int xm_free_graph(xm_graph_t* g);
  * max_bytes bounds the rows' total size: the threshold starts at
  * max(min_len, 32) and doubles until all rows of lists at least that long,
  * in both directions, fit.  *out_min_len (nullable) receives the threshold
- * used, 0 if no row was built.  max_bytes = 0 removes the rows.  Graphs with
- * n >= 2^31 get no rows.  The call synchronises the device (launches in
+ * used, 0 if no row was built.  max_bytes = 0 removes the rows; budgets
+ * above 4 GiB - 256 bytes are treated as that.  Graphs with n >= 2^31 get no
+ * rows.  The call synchronises the device (launches in
  * flight may read the old rows) and fails with XM_ERR_INVALID while captured
  * launches (xm_exec_t) of this graph exist.  Rows cost ceil(n/32)*4 bytes
  * each; XM_ERR_OOM leaves the graph without rows. */
@@ -187,7 +188,9 @@ int xm_plan_work(uint32_t n, const uint32_t* out_off, const uint32_t* out_adj,
 typedef struct xm_count_opts {
     uint32_t struct_size;   /* sizeof(xm_count_opts) */
     uint32_t flags;         /* reserved, must be 0 */
-    uint32_t chunk;         /* roots taken per work grab (default 1, <= 64) */
+    uint32_t chunk;         /* roots taken per work grab (<= 64; default 0: about
+                               64 root tasks per resident wave, i.e.
+                               ceil(roots x plans / (waves x 64)) clamped to 1..64) */
     uint32_t split;         /* a root whose first-level candidate list has L1
                                entries is split into stealable sub-ranges of
                                min(split, split_work / L1) entries (at least 1)

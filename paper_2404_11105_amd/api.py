@@ -40,7 +40,7 @@ class Graph:
     """
 
     DEFAULT_ROW_BYTES = 2 << 30
-    DEFAULT_ROW_MIN = 32
+    DEFAULT_ROW_MIN = 64
 
     def __init__(self, digraph, device: str = "cuda", validate: bool = False, stream=None,
                  dense_rows: int | None = None, row_min: int | None = None):

@@ -49,12 +49,28 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ uint32_t scan_incl(uint32_t v, uint32_t lane) {
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        uint32_t t = __shfl_up(v, d, 64);
-        if (lane >= (uint32_t)d) v += t;
-    }
+// Wave-wide inclusive scans (sum, max) over the 64 lanes with DPP row
+// shifts and row broadcasts: 6 VALU steps, no LDS traffic.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+}
+__device__ __forceinline__ uint32_t scan_incl(uint32_t v, uint32_t) {
+    v += dpp_<0x111, 0xf>(v);  // row_shr:1
+    v += dpp_<0x112, 0xf>(v);  // row_shr:2
+    v += dpp_<0x114, 0xf>(v);  // row_shr:4
+    v += dpp_<0x118, 0xf>(v);  // row_shr:8
+    v += dpp_<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+__device__ __forceinline__ uint32_t scan_max(uint32_t v) {
+    v = max(v, dpp_<0x111, 0xf>(v));
+    v = max(v, dpp_<0x112, 0xf>(v));
+    v = max(v, dpp_<0x114, 0xf>(v));
+    v = max(v, dpp_<0x118, 0xf>(v));
+    v = max(v, dpp_<0x142, 0xa>(v));
+    v = max(v, dpp_<0x143, 0xc>(v));
     return v;
 }
 
@@ -77,23 +93,44 @@ __device__ __forceinline__ const uint32_t* off_of(const DevGraph& g, uint32_t di
     return dir ? g.in_off : g.out_off;
 }
 
-// Membership of x in the list that owns dense row r of direction dir.
-__device__ __forceinline__ bool row_has(const DevGraph& g, uint32_t dir, uint32_t r, uint32_t x) {
-    const uint32_t* row = (dir ? g.rows_in : g.rows_out) + (uint64_t)r * g.row_words;
-    return (row[x >> 5] >> (x & 31u)) & 1u;
+// Word `w` of the dense rows (word offsets are below 2^30: the rows take less
+// than 4 GiB, so the byte offset is a 32-bit register added to the base).
+__device__ __forceinline__ uint32_t row_word(const DevGraph& g, uint32_t w) {
+    return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(g.rows) + (w << 2));
 }
 
 // A probe list (offset o, length l) of node nd becomes a row reference
-// (o = row, l = kRowLen) when the list is long enough to have a row.
+// (o = word offset of the row, l = kRowLen) when the list has a row.
 __device__ __forceinline__ void to_row(const DevGraph& g, uint32_t dir, uint32_t nd, uint32_t& o, uint32_t& l) {
     if (l != kSkip && l >= g.row_min) {
         const uint2 r = g.row_of[nd];
         const uint32_t row = dir ? r.y : r.x;
         if (row != kSkip) {
-            o = row;
+            o = row * g.row_words;
             l = kRowLen;
         }
     }
+}
+
+// Per-level constraint fields, loaded once into scalar registers.
+struct LK {
+    uint32_t n_cons, reuse, inj, deg_check, extra, dirm, dmin_out, dmin_in;
+    uint64_t lvlb;
+    __device__ __forceinline__ uint32_t lvl(uint32_t c) const { return (uint32_t)(lvlb >> (3 * c)) & 7u; }
+    __device__ __forceinline__ uint32_t dir(uint32_t c) const { return (dirm >> c) & 1u; }
+};
+__device__ __forceinline__ LK load_lk(const LevelDesc& D) {
+    LK k;
+    k.n_cons = uni(D.n_cons);
+    k.reuse = uni(D.reuse);
+    k.inj = uni(D.inj);
+    k.deg_check = uni(D.deg_check);
+    k.extra = uni(D.extra);
+    k.dirm = uni(D.dir_mask);
+    k.dmin_out = uni(D.dmin_out);
+    k.dmin_in = uni(D.dmin_in);
+    k.lvlb = ((uint64_t)uni((uint32_t)(D.lvl_bits >> 32)) << 32) | uni((uint32_t)D.lvl_bits);
+    return k;
 }
 
 // Unsigned 128-bit add into (lo, hi) with an overflow flag.
@@ -121,6 +158,7 @@ struct Lds {
     uint32_t* base_kind; // [64]: 0 out list, 1 in list, 2 level buffer
     uint32_t* incl;      // [64]
     uint32_t* segcnt;    // [64]
+    uint32_t* mark;      // [128]: tile parent marks
     uint32_t* chk_off;   // [maxc][64]
     uint32_t* chk_len;   // [maxc][64]
     uint32_t* hist;      // [64][16]
@@ -138,7 +176,8 @@ __device__ __forceinline__ Lds carve(uint32_t* w, uint32_t rows, uint32_t maxc, 
     s.base_kind = q + 128;
     s.incl = q + 192;
     s.segcnt = q + 256;
-    q += 6 * 64;
+    s.mark = q + 384;
+    q += 8 * 64;
     s.chk_off = q;
     s.chk_len = q + maxc * 64;
     q += 2 * maxc * 64;
@@ -186,10 +225,10 @@ __device__ __forceinline__ uint32_t level1_len(const DevGraph& g, const PlanDesc
 
 // Phase A of a level: lane = one partial match (parent) of the window.  Walks
 // the parent chain into LDS (bound nodes, ancestor indices) and picks the base
-// list and the lists to probe.  Returns the base length.
+// list and the lists to probe (long ones as dense rows).  Returns the base
+// length.
 template <bool IS_SIG>
-__device__ uint32_t phase_a(Ctx& C, const LevelDesc& D, uint32_t lv, uint32_t p, bool pv,
-                            bool walk) {
+__device__ uint32_t phase_a(Ctx& C, const LK& D, uint32_t lv, uint32_t p, bool pv, bool walk) {
     const KArgs& a = *C.a;
     const DevGraph& g = a.g;
     const uint32_t lane = C.lane;
@@ -220,11 +259,11 @@ __device__ uint32_t phase_a(Ctx& C, const LevelDesc& D, uint32_t lv, uint32_t p,
             for (uint32_t c = 0; c < D.n_cons; c++) {
                 uint32_t l = kSkip, o = 0;
                 if ((D.extra >> c) & 1u) {
-                    uint32_t nd = C.s.bound[D.cons_lvl[c] * 64 + lane];
-                    const uint32_t* off = off_of(g, D.cons_dir[c]);
+                    const uint32_t nd = C.s.bound[D.lvl(c) * 64 + lane];
+                    const uint32_t* off = off_of(g, D.dir(c));
                     o = off[nd];
                     l = off[nd + 1] - o;
-                    to_row(g, D.cons_dir[c], nd, o, l);
+                    to_row(g, D.dir(c), nd, o, l);
                 }
                 C.s.chk_off[c * 64 + lane] = o;
                 C.s.chk_len[c * 64 + lane] = l;
@@ -235,8 +274,8 @@ __device__ uint32_t phase_a(Ctx& C, const LevelDesc& D, uint32_t lv, uint32_t p,
     if (!fetched) {
         uint32_t best = kSkip, bc = 0, bo = 0;
         for (uint32_t c = 0; c < D.n_cons; c++) {
-            uint32_t nd = C.s.bound[D.cons_lvl[c] * 64 + lane];
-            const uint32_t* off = off_of(g, D.cons_dir[c]);
+            const uint32_t nd = C.s.bound[D.lvl(c) * 64 + lane];
+            const uint32_t* off = off_of(g, D.dir(c));
             uint32_t o = off[nd];
             uint32_t l = off[nd + 1] - o;
             C.s.chk_off[c * 64 + lane] = o;
@@ -252,11 +291,11 @@ __device__ uint32_t phase_a(Ctx& C, const LevelDesc& D, uint32_t lv, uint32_t p,
         for (uint32_t c = 0; c < D.n_cons; c++) {
             uint32_t o = C.s.chk_off[c * 64 + lane], l = C.s.chk_len[c * 64 + lane];
             if (c == bc || l < g.row_min) continue;
-            to_row(g, D.cons_dir[c], C.s.bound[D.cons_lvl[c] * 64 + lane], o, l);
+            to_row(g, D.dir(c), C.s.bound[D.lvl(c) * 64 + lane], o, l);
             C.s.chk_off[c * 64 + lane] = o;
             C.s.chk_len[c * 64 + lane] = l;
         }
-        C.s.base_kind[lane] = D.cons_dir[bc];
+        C.s.base_kind[lane] = D.dir(bc);
         C.s.base_off[lane] = bo;
         len = best;
         if (!IS_SIG && lv == 1) {
@@ -281,118 +320,124 @@ __device__ __forceinline__ uint32_t base_elem(const Ctx& C, uint32_t j, uint32_t
     return adj_of(C.a->g, kind)[off];
 }
 
-// Window parent of flattened element g: smallest j with incl[j] > g.
-__device__ __forceinline__ uint32_t find_parent(const Lds& s, uint32_t np, uint32_t g) {
-    uint32_t lo = 0, n = np;
-    while (n > 0) {
-        uint32_t h = n >> 1;
-        if (s.incl[lo + h] <= g) {
-            lo += h + 1;
-            n -= h + 1;
-        } else {
-            n = h;
-        }
-    }
-    return lo;
+// Window parents of the elements t0 + lane (tile a) and t0 + 64 + lane (tile
+// b) of a flattened pass.  Lane j (a window parent) owns the elements
+// [start, start + len); parents that own elements mark their first one, and a
+// max-scan carries each mark forward.  `carry` is the parent of the last
+// element of the previous step (0 before the first).
+__device__ __forceinline__ void tile_parents(const Lds& s, uint32_t lane, uint32_t t0, uint32_t start, bool owns,
+                                             uint32_t& carry, uint32_t& ja, uint32_t& jb) {
+    s.mark[lane] = 0;
+    s.mark[64 + lane] = 0;
+    wave_sync();
+    if (owns && start >= t0 && start - t0 < 128u) s.mark[start - t0] = lane + 1;
+    wave_sync();
+    const uint32_t ma = scan_max(s.mark[lane]);
+    const uint32_t mb = scan_max(s.mark[64 + lane]);
+    ja = ma ? ma - 1 : carry;
+    const uint32_t last_a = uni(__shfl(ja, 63, 64));
+    jb = mb ? mb - 1 : last_a;
+    carry = uni(__shfl(jb, 63, 64));
 }
 
-// Two independent sorted-list searches interleaved step by step, so each lane
-// keeps two loads in flight instead of one dependent chain.
-__device__ __forceinline__ void contains2(const uint32_t* __restrict__ A, uint32_t la, uint32_t xa, bool& fa,
-                                          const uint32_t* __restrict__ B, uint32_t lb, uint32_t xb, bool& fb) {
-    uint32_t ba = 0, na = fa ? la : 0, bb = 0, nb = fb ? lb : 0;
-    while (na > 1 || nb > 1) {
-        const uint32_t ha = na >> 1, hb = nb >> 1;
-        const uint32_t va = na > 1 ? A[ba + ha] : 0u;
-        const uint32_t vb = nb > 1 ? B[bb + hb] : 0u;
-        if (na > 1) {
-            ba = (va <= xa) ? ba + ha : ba;
-            na -= ha;
-        }
-        if (nb > 1) {
-            bb = (vb <= xb) ? bb + hb : bb;
-            nb -= hb;
-        }
+// Two sorted-list searches per lane (one per element), both loads of a step
+// issued together.  Lanes without a search pass n = 0 (offset 0 is then read
+// and ignored; the caller runs this only when some lane has a non-empty list,
+// so the adjacency array is not empty).
+__device__ __forceinline__ void search2(const uint32_t* __restrict__ adj, uint32_t oa, uint32_t na, uint32_t xa,
+                                        bool& fa, uint32_t ob, uint32_t nb, uint32_t xb, bool& fb) {
+    uint32_t ba = oa, bb = ob, ra = na, rb = nb;
+    while (__ballot(ra > 1 || rb > 1)) {
+        const uint32_t ha = ra >> 1, hb = rb >> 1;
+        const uint32_t va = adj[ba + ha], vb = adj[bb + hb];
+        ba = (va <= xa) ? ba + ha : ba;
+        bb = (vb <= xb) ? bb + hb : bb;
+        ra -= ha;
+        rb -= hb;
     }
-    fa = fa && la > 0 && A[ba] == xa;
-    fb = fb && lb > 0 && B[bb] == xb;
+    const uint32_t ea = adj[ba], eb = adj[bb];
+    fa = na > 0 && ea == xa;
+    fb = nb > 0 && eb == xb;
 }
 
-__device__ __forceinline__ bool check_elem(const Ctx& C, const LevelDesc& D, uint32_t lv, uint32_t j,
-                                           uint32_t x) {
+// Candidate tests of two elements (xa of window parent ja, xb of jb) against
+// level D: injectivity, degree thresholds, then each probe list as a dense-row
+// bit test or a sorted-list search.  oka / okb: in = element valid, out =
+// element passes.
+__device__ __forceinline__ void check_pair(const Ctx& C, const LK& D, uint32_t lv, uint32_t ja, uint32_t xa,
+                                           bool& oka, uint32_t jb, uint32_t xb, bool& okb) {
     const DevGraph& g = C.a->g;
-    bool ok = true;
-    uint32_t inj = D.inj;
     for (uint32_t l = 0; l < lv; l++)
-        if ((inj >> l) & 1u) ok = ok && (x != C.s.bound[l * 64 + j]);
-    if (ok && D.deg_check) {
-        uint2 d = g.deg[x];
-        ok = d.x >= D.dmin_out && d.y >= D.dmin_in;
-    }
-    for (uint32_t c = 0; c < D.n_cons && ok; c++) {
-        uint32_t l = C.s.chk_len[c * 64 + j];
-        if (l == kRowLen)
-            ok = row_has(g, D.cons_dir[c], C.s.chk_off[c * 64 + j], x);
-        else if (l != kSkip)
-            ok = contains(adj_of(g, D.cons_dir[c]) + C.s.chk_off[c * 64 + j], l, x);
-    }
-    return ok;
-}
-
-// check_elem for two elements at once (oka / okb: in = element valid, out = passes).
-__device__ __forceinline__ void check_pair(const Ctx& C, const LevelDesc& D, uint32_t lv, uint32_t ja,
-                                           uint32_t xa, bool& oka, uint32_t jb, uint32_t xb, bool& okb) {
-    const DevGraph& g = C.a->g;
-    const uint32_t inj = D.inj;
-    for (uint32_t l = 0; l < lv; l++)
-        if ((inj >> l) & 1u) {
+        if ((D.inj >> l) & 1u) {
             oka = oka && (xa != C.s.bound[l * 64 + ja]);
             okb = okb && (xb != C.s.bound[l * 64 + jb]);
         }
     if (D.deg_check) {
-        uint2 da = oka ? g.deg[xa] : make_uint2(0, 0);
-        uint2 db = okb ? g.deg[xb] : make_uint2(0, 0);
+        const uint2 da = g.deg[oka ? xa : 0u], db = g.deg[okb ? xb : 0u];
         oka = oka && da.x >= D.dmin_out && da.y >= D.dmin_in;
         okb = okb && db.x >= D.dmin_out && db.y >= D.dmin_in;
     }
     for (uint32_t c = 0; c < D.n_cons; c++) {
         const uint32_t lA = C.s.chk_len[c * 64 + ja], lB = C.s.chk_len[c * 64 + jb];
         const uint32_t oA = C.s.chk_off[c * 64 + ja], oB = C.s.chk_off[c * 64 + jb];
-        const uint32_t dir = D.cons_dir[c];
-        // dense rows: one bit test each
-        if (oka && lA == kRowLen) oka = row_has(g, dir, oA, xa);
-        if (okb && lB == kRowLen) okb = row_has(g, dir, oB, xb);
-        bool fa = oka && lA != kSkip && lA != kRowLen, fb = okb && lB != kSkip && lB != kRowLen;
-        if (!(fa || fb)) continue;
-        const uint32_t* adj = adj_of(g, dir);
-        const bool sa = fa, sb = fb;
-        contains2(adj + oA, lA, xa, fa, adj + oB, lB, xb, fb);
-        if (sa) oka = fa;
-        if (sb) okb = fb;
+        const bool rA = oka && lA == kRowLen, rB = okb && lB == kRowLen;
+        if (__ballot(rA || rB)) {
+            const uint32_t wa = row_word(g, rA ? oA + (xa >> 5) : 0u);
+            const uint32_t wb = row_word(g, rB ? oB + (xb >> 5) : 0u);
+            if (rA) oka = (wa >> (xa & 31u)) & 1u;
+            if (rB) okb = (wb >> (xb & 31u)) & 1u;
+        }
+        // an empty list holds nothing
+        if (lA == 0) oka = false;
+        if (lB == 0) okb = false;
+        const bool sa = oka && lA < kRowLen, sb = okb && lB < kRowLen;
+        if (__ballot(sa || sb)) {
+            bool fa, fb;
+            search2(adj_of(g, D.dir(c)), sa ? oA : 0u, sa ? lA : 0u, xa, fa, sb ? oB : 0u, sb ? lB : 0u, xb, fb);
+            if (sa) oka = fa;
+            if (sb) okb = fb;
+        }
     }
 }
 
-// Membership of x in leaf signature s for window parent j (constraints only;
-// injectivity is common to all leaves and checked by the caller).
-__device__ __forceinline__ bool member_sig(const Ctx& C, const LevelDesc& S, uint32_t j, uint32_t x) {
+// Membership of xa / xb in leaf signature S for window parents ja / jb
+// (constraints only; injectivity is common to all leaves and checked by the
+// caller).  in: element valid; out: member.
+__device__ __forceinline__ void member_pair(const Ctx& C, const LK& S, uint32_t ja, uint32_t xa, bool& ina,
+                                            uint32_t jb, uint32_t xb, bool& inb) {
     const DevGraph& g = C.a->g;
-    bool ok = true;
-    for (uint32_t c = 0; c < S.n_cons && ok; c++) {
-        uint32_t nd = C.s.bound[S.cons_lvl[c] * 64 + j];
-        const uint32_t* off = off_of(g, S.cons_dir[c]);
-        uint32_t o = off[nd];
-        uint32_t l = off[nd + 1] - o;
-        to_row(g, S.cons_dir[c], nd, o, l);
-        ok = (l == kRowLen) ? row_has(g, S.cons_dir[c], o, x) : contains(adj_of(g, S.cons_dir[c]) + o, l, x);
+    for (uint32_t c = 0; c < S.n_cons; c++) {
+        const uint32_t dir = S.dir(c), lvl = S.lvl(c);
+        const uint32_t* off = off_of(g, dir);
+        const uint32_t na = ina ? C.s.bound[lvl * 64 + ja] : 0u, nb = inb ? C.s.bound[lvl * 64 + jb] : 0u;
+        uint32_t oA = off[na], lA = off[na + 1] - oA;
+        uint32_t oB = off[nb], lB = off[nb + 1] - oB;
+        if (ina) to_row(g, dir, na, oA, lA);
+        if (inb) to_row(g, dir, nb, oB, lB);
+        const bool rA = ina && lA == kRowLen, rB = inb && lB == kRowLen;
+        if (__ballot(rA || rB)) {
+            const uint32_t wa = row_word(g, rA ? oA + (xa >> 5) : 0u);
+            const uint32_t wb = row_word(g, rB ? oB + (xb >> 5) : 0u);
+            if (rA) ina = (wa >> (xa & 31u)) & 1u;
+            if (rB) inb = (wb >> (xb & 31u)) & 1u;
+        }
+        if (lA == 0) ina = false;
+        if (lB == 0) inb = false;
+        const bool sa = ina && lA < kRowLen, sb = inb && lB < kRowLen;
+        if (__ballot(sa || sb)) {
+            bool fa, fb;
+            search2(adj_of(g, dir), sa ? oA : 0u, sa ? lA : 0u, xa, fa, sb ? oB : 0u, sb ? lB : 0u, xb, fb);
+            if (sa) ina = fa;
+            if (sb) inb = fb;
+        }
     }
-    return ok;
 }
 
 // Expand one window of level lv from the parents in level lv-1.  Returns the
 // number of children written to level lv's buffer.
 __device__ uint32_t expand(Ctx& C, uint32_t lv) {
     const KArgs& a = *C.a;
-    const LevelDesc& D = C.P->lvl[lv];
+    const LK D = load_lk(C.P->lvl[lv]);
     const uint32_t lane = C.lane;
     uint32_t* st = C.s.st;
     const uint32_t nparents = uni(st[16 + lv - 1]);
@@ -415,28 +460,32 @@ __device__ uint32_t expand(Ctx& C, uint32_t lv) {
         T = cap;
         partial = true;
         np = 1;
+        if (lane == 0) incl = len = cap;
         C.s.incl[0] = cap;
     } else {
         T = uni(__shfl(incl, (int)np - 1, 64));
     }
+    // lane j < np owns the elements [incl - len, incl)
+    const bool owns = lane < np && len > 0;
+    const uint32_t start = incl - len;
     wave_sync();
     Lvl Fo = lvl_arrays(C.scr, cap, lv);
-    uint32_t nout = 0;
+    uint32_t nout = 0, carry = 0;
     const uint32_t reuse = D.reuse;
     // two tiles per step: survivors of tile a are written before those of
     // tile b, so each parent's children stay contiguous and in order
     for (uint32_t t0 = 0; t0 < T; t0 += 128) {
         const uint32_t ga = t0 + lane, gb = t0 + 64 + lane;
+        uint32_t ja, jb;
+        tile_parents(C.s, lane, t0, start, owns, carry, ja, jb);
         bool oka = ga < T, okb = gb < T;
-        uint32_t ja = 0, xa = 0, jb = 0, xb = 0;
-        if (oka) {
-            ja = find_parent(C.s, np, ga);
-            xa = base_elem(C, ja, ga - (ja ? C.s.incl[ja - 1] : 0) + (ja == 0 ? pofs : 0), reuse);
-        }
-        if (okb) {
-            jb = find_parent(C.s, np, gb);
-            xb = base_elem(C, jb, gb - (jb ? C.s.incl[jb - 1] : 0) + (jb == 0 ? pofs : 0), reuse);
-        }
+        uint32_t xa = 0, xb = 0;
+        const uint32_t la = ga - (ja ? C.s.incl[ja - 1] : 0u) + (ja == 0 ? pofs : 0u);
+        const uint32_t lb = gb - (jb ? C.s.incl[jb - 1] : 0u) + (jb == 0 ? pofs : 0u);
+        oka = oka && la < C.s.base_len[ja];
+        okb = okb && lb < C.s.base_len[jb];
+        if (oka) xa = base_elem(C, ja, la, reuse);
+        if (okb) xb = base_elem(C, jb, lb, reuse);
         check_pair(C, D, lv, ja, xa, oka, jb, xb, okb);
         const uint64_t ma = __ballot(oka);
         if (oka) {
@@ -542,9 +591,10 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
     const KArgs& a = *C.a;
     const PlanDesc* P = C.P;
     const uint32_t lane = C.lane;
-    const uint32_t nsig = P->n_sig;
+    const uint32_t nsig = uni(P->n_sig);
     const bool linear = !NONLIN || P->linear != 0;
     const uint32_t nb = lv + 1;  // bound levels 0..lv
+    const LK S0 = load_lk(P->sig[0]);
     for (uint32_t w0 = 0; w0 < nprefix; w0 += 64) {
         const uint32_t p = w0 + lane;
         const bool pv = p < nprefix;
@@ -562,20 +612,19 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
             for (int q = 0; q < 16; q++) C.s.hist[lane * 16 + q] = 0;
         }
         unsigned long long lin = 0;
-        if (linear && P->sig[0].n_cons == 1 && P->sig[0].reuse == kNoReuse) {
+        if (linear && S0.n_cons == 1 && S0.reuse == kNoReuse) {
             // one leaf drawn from one list L: |L| minus the bound nodes found in L
-            const LevelDesc& S = P->sig[0];
             uint32_t v = 0;
             if (pv) {
                 const DevGraph& g = a.g;
-                uint32_t nd = C.s.bound[S.cons_lvl[0] * 64 + lane];
-                const uint32_t* off = off_of(g, S.cons_dir[0]);
+                uint32_t nd = C.s.bound[S0.lvl(0) * 64 + lane];
+                const uint32_t* off = off_of(g, S0.dir(0));
                 uint32_t o = off[nd];
                 uint32_t l = off[nd + 1] - o;
-                const uint32_t* L = adj_of(g, S.cons_dir[0]) + o;
+                const uint32_t* L = adj_of(g, S0.dir(0)) + o;
                 v = l;
                 for (uint32_t b = 0; b < nb; b++)
-                    if (((S.inj >> b) & 1u) && contains(L, l, C.s.bound[b * 64 + lane])) v -= 1;
+                    if (((S0.inj >> b) & 1u) && contains(L, l, C.s.bound[b * 64 + lane])) v -= 1;
             }
             unsigned long long o = C.acc_lo;
             C.acc_lo += v;
@@ -585,7 +634,7 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
         }
         for (uint32_t s = 0; s < nsig; s++) {
             if (!P->sig_scan[s]) continue;
-            const LevelDesc& S = P->sig[s];
+            const LK S = load_lk(P->sig[s]);
             uint32_t len = phase_a<true>(C, S, nb, p, pv, false);
             // one leaf whose set is a base list and one probe list: balanced big
             // pairs leave the flattened pass for the cooperative merge
@@ -606,48 +655,44 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
             }
             uint64_t bigmask = __ballot(big);
             if (big) len = 0;
-            uint32_t incl = scan_incl(len, lane);
+            const uint32_t incl = scan_incl(len, lane);
             C.s.incl[lane] = incl;
             const uint32_t T = uni(__shfl(incl, 63, 64));
-            const uint32_t np = 64;
+            const bool owns = len > 0;
+            const uint32_t start = incl - len;
             wave_sync();
             const uint8_t implied = P->sig_implied[s];
             const uint8_t test = P->sig_test[s];
             const uint32_t below = (1u << s) - 1u;
-            if (linear) {
-                // one leaf: survivors are only counted; two tiles per step
-                for (uint32_t t0 = 0; t0 < T; t0 += 128) {
-                    const uint32_t ga = t0 + lane, gb = t0 + 64 + lane;
-                    bool oka = ga < T, okb = gb < T;
-                    uint32_t ja = 0, xa = 0, jb = 0, xb = 0;
-                    if (oka) {
-                        ja = find_parent(C.s, np, ga);
-                        xa = base_elem(C, ja, ga - (ja ? C.s.incl[ja - 1] : 0), S.reuse);
-                    }
-                    if (okb) {
-                        jb = find_parent(C.s, np, gb);
-                        xb = base_elem(C, jb, gb - (jb ? C.s.incl[jb - 1] : 0), S.reuse);
-                    }
-                    check_pair(C, S, nb, ja, xa, oka, jb, xb, okb);
+            uint32_t carry = 0;
+            // two tiles per step
+            for (uint32_t t0 = 0; t0 < T; t0 += 128) {
+                const uint32_t ga = t0 + lane, gb = t0 + 64 + lane;
+                uint32_t ja, jb;
+                tile_parents(C.s, lane, t0, start, owns, carry, ja, jb);
+                const uint32_t la = ga - (ja ? C.s.incl[ja - 1] : 0u);
+                const uint32_t lb = gb - (jb ? C.s.incl[jb - 1] : 0u);
+                bool oka = ga < T && la < C.s.base_len[ja];
+                bool okb = gb < T && lb < C.s.base_len[jb];
+                uint32_t xa = 0, xb = 0;
+                if (oka) xa = base_elem(C, ja, la, S.reuse);
+                if (okb) xb = base_elem(C, jb, lb, S.reuse);
+                check_pair(C, S, nb, ja, xa, oka, jb, xb, okb);
+                if (linear) {
+                    // one leaf: survivors are only counted
                     lin += (unsigned long long)(__popcll(__ballot(oka)) + __popcll(__ballot(okb)));
-                }
-            } else {
-                for (uint32_t t0 = 0; t0 < T; t0 += 64) {
-                    uint32_t gi = t0 + lane;
-                    bool ok = gi < T;
-                    uint32_t j = 0, x = 0;
-                    if (ok) {
-                        j = find_parent(C.s, np, gi);
-                        uint32_t local = gi - (j ? C.s.incl[j - 1] : 0);
-                        x = base_elem(C, j, local, S.reuse);
-                        ok = check_elem(C, S, nb, j, x);
+                } else {
+                    uint32_t mask_a = implied, mask_b = implied;
+#pragma unroll
+                    for (uint32_t s2 = 0; s2 < (uint32_t)kMaxSig; s2++) {
+                        if (s2 >= nsig || !((test >> s2) & 1u)) continue;
+                        bool ia = oka, ib = okb;
+                        member_pair(C, load_lk(P->sig[s2]), ja, xa, ia, jb, xb, ib);
+                        if (ia) mask_a |= 1u << s2;
+                        if (ib) mask_b |= 1u << s2;
                     }
-                    if (ok) {
-                        uint32_t mask = implied;
-                        for (uint32_t s2 = 0; s2 < nsig; s2++)
-                            if (((test >> s2) & 1u) && member_sig(C, P->sig[s2], j, x)) mask |= 1u << s2;
-                        if ((mask & below) == 0) atomicAdd(&C.s.hist[j * 16 + mask], 1u);
-                    }
+                    if (oka && (mask_a & below) == 0) atomicAdd(&C.s.hist[ja * 16 + mask_a], 1u);
+                    if (okb && (mask_b & below) == 0) atomicAdd(&C.s.hist[jb * 16 + mask_b], 1u);
                 }
             }
             wave_sync();
@@ -666,7 +711,7 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
                 const uint32_t plen = uni(C.s.chk_len[pc * 64 + j]);
                 const uint32_t* A = (kind == 2) ? lvl_arrays(C.scr, a.cap, S.reuse).node + boff
                                                 : adj_of(a.g, kind) + boff;
-                const uint32_t* B = adj_of(a.g, S.cons_dir[pc]) + poff;
+                const uint32_t* B = adj_of(a.g, S.dir(pc)) + poff;
                 lin += merge_count(C.s, A, blen, B, plen, S.inj, nb, j, lane);
             }
         }

@@ -34,16 +34,19 @@ struct DevGraph {
     const uint2* deg;   // (out-degree, in-degree)
     uint32_t n;
     uint32_t row_min;   // lists at least this long have a dense row (kNoRows: none)
-    // dense membership rows of long lists: row r of a direction is row_words
-    // uint32 words, bit x set iff node x is in the list
-    const uint32_t* rows_out;
-    const uint32_t* rows_in;
+    // dense membership rows of long lists: row r is row_words uint32 words at
+    // word offset r * row_words (out rows first, then in rows; < 4 GiB in
+    // all), bit x set iff node x is in the list
+    const uint32_t* rows;
     const uint2* row_of;  // per node: (out row, in row), 0xFFFFFFFF = no row
-    uint64_t row_words;
+    uint32_t row_words;
+    uint32_t pad;
 };
 
 constexpr uint32_t kNoRows = 0xFFFFFFFFu;
 constexpr uint32_t kRowLen = 0xFFFFFFFEu;  // probe-list length marker: test a dense row
+
+constexpr uint64_t kMaxRowBytes = (4ull << 30) - 256;  // rows are addressed by 32-bit byte offsets
 
 // Set the bits of dense rows [0, n_rows): row r holds the out-list (r <
 // n_out_rows) or in-list of node row_node[r].  Rows must be zeroed first.
@@ -107,7 +110,8 @@ __host__ __device__ inline uint32_t item_size(uint32_t L1, uint32_t split, uint3
 // the batch), the largest constraint count, and the optional parts.
 inline uint32_t lds_words_for(uint32_t rows, uint32_t maxc, bool nonlinear, bool merge) {
     return 2 * rows * 64       // bound values, ancestor indices
-           + 6 * 64            // base offset/length/kind, inclusive scan, segment counts, spare
+           + 8 * 64            // base offset/length/kind, inclusive scan, segment counts, spare,
+                               // tile parent marks (2 x 64)
            + 2 * maxc * 64     // check-list offset/length per constraint
            + (merge ? kMergeChunk : 0)  // merge chunk
            + (nonlinear ? 16 * 64 : 0)  // leaf-group histograms

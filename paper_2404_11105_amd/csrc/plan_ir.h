@@ -42,10 +42,11 @@ struct LevelDesc {
     uint8_t inj;                  // bit j: check x != phi(v_j)
     uint8_t deg_check;            // 1: check degree thresholds
     uint16_t extra;               // when reusing: bit c -> check constraint c
-    uint16_t pad0;
+    uint16_t dir_mask;            // bit c = cons_dir[c] (packed copy for the kernel)
     uint8_t cons_lvl[kMaxCons];
     uint8_t cons_dir[kMaxCons];   // 0: out(phi(v_j)), 1: in(phi(v_j))
     uint32_t dmin_out, dmin_in;
+    uint64_t lvl_bits;            // cons_lvl[c] at bits [3c, 3c+3) (packed copy)
 };
 
 struct Term {

@@ -646,6 +646,17 @@ int build_plan(uint32_t k, uint32_t n_arcs, const uint8_t* arcs, uint32_t flags,
     for (size_t i = 0; i < terms.size(); i++) D.terms[i] = terms[i];
     D.linear = (D.t == 1) ? 1 : 0;
     for (size_t i = 0; i < best.leaves.size(); i++) D.order[D.e + i] = (uint8_t)best.leaves[i];
+    // packed constraint fields read by the kernel
+    auto pack = [](LevelDesc& L) {
+        L.dir_mask = 0;
+        L.lvl_bits = 0;
+        for (int c = 0; c < L.n_cons; c++) {
+            L.dir_mask |= (uint16_t)((L.cons_dir[c] & 1u) << c);
+            L.lvl_bits |= (uint64_t)(L.cons_lvl[c] & 7u) << (3 * c);
+        }
+    };
+    for (uint32_t i = 1; i < D.e; i++) pack(D.lvl[i]);
+    for (uint32_t g = 0; g < D.n_sig; g++) pack(D.sig[g]);
     json = plan_json(p, D, cr, reduced, best.cost);
     return 0;
 }

@@ -108,7 +108,7 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
     if (n_plans == 0 || !plans) return fail(XM_ERR_INVALID, "no plans");
     if (o && o->struct_size != 0 && o->struct_size < sizeof(xm_count_opts))
         return fail(XM_ERR_INVALID, "xm_count_opts.struct_size too small");
-    L.chunk = (o && o->chunk) ? o->chunk : 1;
+    L.chunk = (o && o->chunk) ? o->chunk : 0;  // 0: sized below from the task count
     L.split = (o && o->split) ? o->split : 64;
     L.split_work = (o && o->split_work) ? o->split_work : 4096;
     L.cap = (o && o->cap) ? o->cap : 4096;
@@ -146,6 +146,14 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
     L.n_waves = (uint32_t)g->n_cu * L.waves_per_cu;
     L.n_waves = (L.n_waves + xm::kWavesPerBlock - 1) / xm::kWavesPerBlock * xm::kWavesPerBlock;
     L.n_blocks = L.n_waves / xm::kWavesPerBlock;
+    if (L.chunk == 0) {
+        // about 64 root tasks per wave: one root per task on small batches,
+        // up to 64 roots per task when plans x roots is large (each task has a
+        // fixed cost: a queue grab, the root filter, a flush)
+        const uint64_t n_src = (o && o->roots_dev) ? o->n_roots : g->n;
+        const uint64_t per = (uint64_t)L.n_waves * 64;
+        L.chunk = (uint32_t)std::min<uint64_t>(64, std::max<uint64_t>(1, (n_src * n_plans + per - 1) / per));
+    }
     if ((size_t)L.lds_words * 4 * xm::kWavesPerBlock > g->max_lds_block)
         return fail(XM_ERR_INVALID, "plans need more LDS than a workgroup may use");
     // split task queue capacity
@@ -222,10 +230,9 @@ int enqueue_count(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const*
     a.g.deg = g->deg;
     a.g.n = g->n;
     a.g.row_min = g->rows ? g->row_min : xm::kNoRows;
-    a.g.rows_out = g->rows;
-    a.g.rows_in = g->rows ? g->rows + (uint64_t)g->n_rows_out * g->row_words : nullptr;
+    a.g.rows = g->rows;
     a.g.row_of = g->row_of;
-    a.g.row_words = g->row_words;
+    a.g.row_words = (uint32_t)g->row_words;
     a.plans = reinterpret_cast<const PlanDesc*>(base + L.off_table);
     a.n_plans = n_plans;
     a.chunk = L.chunk;
@@ -521,6 +528,7 @@ int xm_graph_dense_rows(xm_graph_t* g, uint64_t max_bytes, uint32_t min_len, voi
     g->n_rows_out = g->n_rows_in = 0;
     g->row_words = 0;
     if (max_bytes == 0 || g->n >= 0x80000000u) return XM_OK;
+    max_bytes = std::min<uint64_t>(max_bytes, xm::kMaxRowBytes);
     const uint64_t words = ((uint64_t)g->n + 31) / 32;
     const uint64_t row_bytes = words * 4;
     // the smallest threshold (doubling from min_len, at least 32) whose rows fit
@@ -546,7 +554,7 @@ int xm_graph_dense_rows(xm_graph_t* g, uint64_t max_bytes, uint32_t min_len, voi
         }
     for (uint32_t v = 0; v < g->n; v++)
         if (g->hdeg[v].y >= t) {
-            row_of[v].y = (uint32_t)(row_node.size() - n_out);
+            row_of[v].y = (uint32_t)row_node.size();  // in rows follow the out rows
             row_node.push_back(v);
         }
     uint32_t* rn = nullptr;
@@ -570,7 +578,7 @@ int xm_graph_dense_rows(xm_graph_t* g, uint64_t max_bytes, uint32_t min_len, voi
     dg.in_off = g->in_off;
     dg.in_adj = g->in_adj;
     dg.n = g->n;
-    dg.row_words = words;
+    dg.row_words = (uint32_t)words;
     if ((e = hipMemsetAsync(g->rows, 0, (n_out + n_in) * row_bytes, stream)) != hipSuccess ||
         (e = hipMemcpyAsync(g->row_of, row_of.data(), (size_t)g->n * sizeof(uint2), hipMemcpyHostToDevice,
                             stream)) != hipSuccess ||

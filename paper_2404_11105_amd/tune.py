@@ -5,7 +5,7 @@ parameters that only change speed, never the counts:
 
   split_work  target work of a stealable first-level task (hub splitting)
   split       largest first-level sub-range of a split root
-  chunk       roots per root task
+  chunk       roots per root task (0: sized from the task count)
   waves_per_cu resident waves (0 = from occupancy)
   merge_min   cooperative merge threshold (0xFFFFFFFF = off)
 
@@ -16,11 +16,10 @@ timed with HIP events on the launch stream (one warm-up, then the median of
 return the same counts, else the tuner raises.  Results are cached in a
 JSON file keyed by the graph's size and the plans' descriptions.
 
-Each trial's first launch runs under a Watchdog: a candidate that has not
-finished within a few times the best time so far is cancelled on the device
-and counted as slower; the default configuration gets `first_budget_s`, and
-raises if it does not finish within it.  Timed repetitions reuse the
-launch that completed, so they run without the flag.
+Every launch runs under a Watchdog: a trial that has not finished within a
+few times the best time so far is cancelled on the device and counted as
+slower; the default configuration gets `first_budget_s`, and the tuner
+raises if it does not finish within it.
 """
 from __future__ import annotations
 
@@ -32,11 +31,11 @@ import time
 SPACE = [
     ("split_work", [4096, 16384, 65536]),
     ("split", [64, 128, 512]),
-    ("chunk", [1, 4, 16]),
+    ("chunk", [0, 1, 4, 16, 64]),
     ("waves_per_cu", [0, 16, 32]),
     ("merge_min", [0xFFFFFFFF, 64]),
 ]
-DEFAULTS = dict(split_work=4096, split=64, chunk=1, waves_per_cu=0, merge_min=0xFFFFFFFF)
+DEFAULTS = dict(split_work=4096, split=64, chunk=0, waves_per_cu=0, merge_min=0xFFFFFFFF)
 
 
 def signature(graph, plans) -> str:
@@ -49,37 +48,34 @@ def signature(graph, plans) -> str:
 
 
 def time_launch(graph, plans, stream, reps: int = 3, watchdog=None, budget_s: float = 0.0,
-                **opts):
+                log=None, **opts):
     """Median GPU milliseconds of one batched launch, and its counts.
 
-    With a watchdog, the first launch is cancelled after budget_s seconds;
-    then (inf, None) is returned."""
+    One untimed launch, then `reps` timed ones; with a watchdog every launch
+    is cancelled after budget_s seconds, and then (inf, None) is returned."""
     import torch
     from .api import Counter
-    if watchdog is not None:
-        probe = Counter(graph, plans, cancel=watchdog, **opts)
-        watchdog.arm(budget_s)
-        probe.run(stream)
-        stream.synchronize()
-        watchdog.disarm()
-        counts, status = probe.results()
-        del probe
-        if any(s == -7 for s in status):
-            return float("inf"), None
-    c = Counter(graph, plans, **opts)
-    c.run(stream)
-    stream.synchronize()
-    counts, status = c.results()
-    if any(s != 0 for s in status):
-        raise RuntimeError(f"launch status {status} with {opts}")
+    c = Counter(graph, plans, cancel=watchdog, **opts)
     ms = []
-    for _ in range(reps):
+    for i in range(reps + 1):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        if watchdog is not None:
+            watchdog.arm(budget_s)
         e0.record(stream)
         c.run(stream)
         e1.record(stream)
         stream.synchronize()
-        ms.append(e0.elapsed_time(e1))
+        if watchdog is not None:
+            watchdog.disarm()
+        counts, status = c.results()
+        if any(s == -7 for s in status):
+            return float("inf"), None
+        if any(s != 0 for s in status):
+            raise RuntimeError(f"launch status {status} with {opts}")
+        if log:
+            log(f"[tune]   launch {i}: {e0.elapsed_time(e1):.1f} ms")
+        if i:
+            ms.append(e0.elapsed_time(e1))
     ms.sort()
     return ms[len(ms) // 2], counts
 
@@ -99,7 +95,9 @@ def tune(graph, plans, stream=None, cache_path: str | None = None, reps: int = 3
     t0 = time.time()
     best = dict(DEFAULTS)
     wd = Watchdog()
-    best_ms, ref_counts = time_launch(graph, plans, stream, reps, wd, first_budget_s, **best)
+    if log:
+        log(f"[tune] default {best}")
+    best_ms, ref_counts = time_launch(graph, plans, stream, reps, wd, first_budget_s, log, **best)
     if ref_counts is None:
         raise RuntimeError(f"default launch did not finish within {first_budget_s} s")
     trials = [(dict(best), best_ms)]
@@ -109,7 +107,7 @@ def tune(graph, plans, stream=None, cache_path: str | None = None, reps: int = 3
                 continue
             cand = dict(best, **{name: v})
             ms, counts = time_launch(graph, plans, stream, reps, wd,
-                                     max(1.0, 4e-3 * best_ms), **cand)
+                                     max(1.0, 4e-3 * best_ms), None, **cand)
             if counts is None:
                 if log:
                     log(f"[tune] {name}={v}: cancelled after {max(1.0, 4e-3 * best_ms):.1f} s")
