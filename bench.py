@@ -260,7 +260,13 @@ def bench_serve(args):
             if d > 0:
                 time.sleep(d)
             futs.append(srv.submit(gid, p))
-        res = [f.result() for f in futs]
+            if len(futs) % 50 == 0:
+                log(f"[serve]   submitted {len(futs)}")
+        res = []
+        for f in futs:
+            res.append(f.result())
+            if len(res) % 50 == 0:
+                log(f"[serve]   completed {len(res)}")
         srv.close()
         st = srv.stats()
         st.update(qps=qps, load=frac)

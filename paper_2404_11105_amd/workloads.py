@@ -8,9 +8,9 @@ work cap: the plan's algorithmic work (xm_plan_work) is estimated from roots
 sampled by degree rank -- all of the 16 largest, then 16 seeded roots from
 each rank stratum [16,64), [64,256), ..., [262144, n), each weighted by its
 stratum size -- and must stay under CAP_ELEMENTS, with no walk passing
-WALK_BUDGET partial matches; the estimates of all accepted patterns together
-stay under TOTAL_CAP (a candidate that would pass it is rejected), which
-keeps one batched launch at a few seconds.  Sizes are drawn round-robin (3, 4, 5, 6) with a
+WALK_BUDGET partial matches; the estimates of the accepted heavy patterns
+(above HEAVY elements) together stay under TOTAL_CAP (a heavy candidate that
+would pass it is rejected), which keeps one batched launch at a few seconds.  Sizes are drawn round-robin (3, 4, 5, 6) with a
 quota of 64 each; a size whose candidates run out (MAX_DRAWS) is backfilled
 by smaller sizes.  The accepted seeds are stored in workloads/batch256.json
 with the counts of rejected draws.
@@ -30,6 +30,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 BATCH_PATH = os.path.join(HERE, "workloads", "batch256.json")
 CAP_ELEMENTS = 3e11
 TOTAL_CAP = 4e12
+HEAVY = 1e10
 WALK_BUDGET = 2_000_000
 STRATA = [0, 16, 64, 256, 1024, 4096, 16384, 65536, 262144]
 MAX_DRAWS = 1000
@@ -87,7 +88,7 @@ def select_batch(threads: int = 8):
                 if r["exceeded"] or e > CAP_ELEMENTS:
                     exceeded = True
                     break
-            if exceeded or sum(est) + e > TOTAL_CAP:
+            if exceeded or (e > HEAVY and sum(x for x in est if x > HEAVY) + e > TOTAL_CAP):
                 rejected[k] += 1
                 continue
             accepted.append((k, seed))
@@ -107,7 +108,7 @@ def select_batch(threads: int = 8):
                 break
     rec = {"graph": "rmat(scale=22, edge_factor=16, abcd=(.57,.19,.19,.05), seed=0)",
            "recipe": "random_pattern(k, seed); work cap from a degree-stratified root sample",
-           "cap_elements": CAP_ELEMENTS, "total_cap": TOTAL_CAP, "walk_budget": WALK_BUDGET,
+           "cap_elements": CAP_ELEMENTS, "total_cap": TOTAL_CAP, "heavy": HEAVY, "walk_budget": WALK_BUDGET,
            "accepted": accepted, "estimated_elements": est,
            "rejected_per_k": rejected, "draws_per_k": draws,
            "selection_seconds": round(time.time() - t0, 1)}
