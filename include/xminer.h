@@ -98,12 +98,12 @@ int xm_free_graph(xm_graph_t* g);
  * owns, and xm_count then answers such a test with one load instead of a
  * search of the sorted list.  Counts do not change.
  *
- * max_bytes bounds the rows' total size: the threshold starts at
- * max(min_len, 32) and doubles until all rows of lists at least that long,
- * in both directions, fit.  *out_min_len (nullable) receives the threshold
- * used, 0 if no row was built.  max_bytes = 0 removes the rows; budgets
- * above 4 GiB - 256 bytes are treated as that.  Graphs with n >= 2^31 get no
- * rows.  The call synchronises the device (launches in
+ * max_bytes bounds the rows' total size: the threshold is the smallest
+ * list length, at least max(min_len, 32), such that every out- and in-list
+ * at least that long gets a row within max_bytes (the longest lists first).
+ * *out_min_len (nullable) receives the threshold used, 0 if no row was
+ * built.  max_bytes = 0 removes the rows; budgets above 16 GiB - 256 bytes
+ * are treated as that.  Graphs with n >= 2^31 get no rows.  The call synchronises the device (launches in
  * flight may read the old rows) and fails with XM_ERR_INVALID while captured
  * launches (xm_exec_t) of this graph exist.  Rows cost ceil(n/32)*4 bytes
  * each; XM_ERR_OOM leaves the graph without rows. */
@@ -176,8 +176,9 @@ int xm_plan_work(uint32_t n, const uint32_t* out_off, const uint32_t* out_adj,
  * counts_dev: caller device buffer of 2*n_plans uint64: (lo, hi) of the
  *             unsigned 128-bit count of plan i at [2i], [2i+1].
  * status_dev: caller device buffer of n_plans int32: XM_OK, XM_ERR_OVERFLOW
- *             (total exceeded 2^128 - 1; counts then wrap) or
- *             XM_ERR_CANCELLED.
+ *             (total exceeded 2^128 - 1; counts then wrap),
+ *             XM_ERR_CANCELLED, or XM_ERR_INVALID (an internal consistency
+ *             check of the launch failed; counts are then not valid).
  * workspace:  caller device buffer of at least xm_workspace_size(...) bytes,
  *             same n_plans, plans and opts.  Its contents are scratch; the
  *             call initialises what it needs on the stream.  Calls that share

@@ -39,7 +39,7 @@ class Graph:
     dense_rows=0 keeps every membership test a sorted-list search.
     """
 
-    DEFAULT_ROW_BYTES = 2 << 30
+    DEFAULT_ROW_BYTES = 8 << 30
     DEFAULT_ROW_MIN = 64
 
     def __init__(self, digraph, device: str = "cuda", validate: bool = False, stream=None,

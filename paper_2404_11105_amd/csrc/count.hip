@@ -93,11 +93,9 @@ __device__ __forceinline__ const uint32_t* off_of(const DevGraph& g, uint32_t di
     return dir ? g.in_off : g.out_off;
 }
 
-// Word `w` of the dense rows (word offsets are below 2^30: the rows take less
-// than 4 GiB, so the byte offset is a 32-bit register added to the base).
-__device__ __forceinline__ uint32_t row_word(const DevGraph& g, uint32_t w) {
-    return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(g.rows) + (w << 2));
-}
+// Word `w` of the dense rows (the rows take less than 16 GiB, so word
+// offsets fit 32 bits).
+__device__ __forceinline__ uint32_t row_word(const DevGraph& g, uint32_t w) { return g.rows[w]; }
 
 // A probe list (offset o, length l) of node nd becomes a row reference
 // (o = word offset of the row, l = kRowLen) when the list has a row.
@@ -119,9 +117,14 @@ struct LK {
     __device__ __forceinline__ uint32_t lvl(uint32_t c) const { return (uint32_t)(lvlb >> (3 * c)) & 7u; }
     __device__ __forceinline__ uint32_t dir(uint32_t c) const { return (dirm >> c) & 1u; }
 };
-__device__ __forceinline__ LK load_lk(const LevelDesc& D) {
+__device__ __forceinline__ LK load_lk(const LevelDesc& D, const KArgs& a) {
     LK k;
     k.n_cons = uni(D.n_cons);
+    if (k.n_cons > a.maxc) {
+        // the per-wave probe arrays hold maxc constraints: never index past them
+        atomicOr(&a.ctl[kCtlBadPlan], 1u);
+        k.n_cons = a.maxc;
+    }
     k.reuse = uni(D.reuse);
     k.inj = uni(D.inj);
     k.deg_check = uni(D.deg_check);
@@ -400,44 +403,11 @@ __device__ __forceinline__ void check_pair(const Ctx& C, const LK& D, uint32_t l
     }
 }
 
-// Membership of xa / xb in leaf signature S for window parents ja / jb
-// (constraints only; injectivity is common to all leaves and checked by the
-// caller).  in: element valid; out: member.
-__device__ __forceinline__ void member_pair(const Ctx& C, const LK& S, uint32_t ja, uint32_t xa, bool& ina,
-                                            uint32_t jb, uint32_t xb, bool& inb) {
-    const DevGraph& g = C.a->g;
-    for (uint32_t c = 0; c < S.n_cons; c++) {
-        const uint32_t dir = S.dir(c), lvl = S.lvl(c);
-        const uint32_t* off = off_of(g, dir);
-        const uint32_t na = ina ? C.s.bound[lvl * 64 + ja] : 0u, nb = inb ? C.s.bound[lvl * 64 + jb] : 0u;
-        uint32_t oA = off[na], lA = off[na + 1] - oA;
-        uint32_t oB = off[nb], lB = off[nb + 1] - oB;
-        if (ina) to_row(g, dir, na, oA, lA);
-        if (inb) to_row(g, dir, nb, oB, lB);
-        const bool rA = ina && lA == kRowLen, rB = inb && lB == kRowLen;
-        if (__ballot(rA || rB)) {
-            const uint32_t wa = row_word(g, rA ? oA + (xa >> 5) : 0u);
-            const uint32_t wb = row_word(g, rB ? oB + (xb >> 5) : 0u);
-            if (rA) ina = (wa >> (xa & 31u)) & 1u;
-            if (rB) inb = (wb >> (xb & 31u)) & 1u;
-        }
-        if (lA == 0) ina = false;
-        if (lB == 0) inb = false;
-        const bool sa = ina && lA < kRowLen, sb = inb && lB < kRowLen;
-        if (__ballot(sa || sb)) {
-            bool fa, fb;
-            search2(adj_of(g, dir), sa ? oA : 0u, sa ? lA : 0u, xa, fa, sb ? oB : 0u, sb ? lB : 0u, xb, fb);
-            if (sa) ina = fa;
-            if (sb) inb = fb;
-        }
-    }
-}
-
 // Expand one window of level lv from the parents in level lv-1.  Returns the
 // number of children written to level lv's buffer.
 __device__ uint32_t expand(Ctx& C, uint32_t lv) {
     const KArgs& a = *C.a;
-    const LK D = load_lk(C.P->lvl[lv]);
+    const LK D = load_lk(C.P->lvl[lv], a);
     const uint32_t lane = C.lane;
     uint32_t* st = C.s.st;
     const uint32_t nparents = uni(st[16 + lv - 1]);
@@ -585,6 +555,94 @@ __device__ uint32_t merge_count(const Lds& s, const uint32_t* __restrict__ A, ui
     return cnt;
 }
 
+// Survivors of this step's two tiles that belong to the parent owning the
+// elements [start, start + len).
+__device__ __forceinline__ uint32_t own_count(uint64_t ballot, uint32_t start, uint32_t len, uint32_t base) {
+    const uint32_t lo = start > base ? start : base;
+    const uint32_t end = start + len, top = base + 64;
+    const uint32_t hi = end < top ? end : top;
+    if (hi <= lo) return 0;
+    const uint32_t a = lo - base, b = hi - base;
+    const uint64_t m = (b == 64 ? ~0ull : ((1ull << b) - 1ull)) & ~((1ull << a) - 1ull);
+    return (uint32_t)__popcll(ballot & m);
+}
+
+// Leaf group with several signatures: for every signature mask M the terms
+// use, h[M] = |intersection over s in M of S_s| is measured per partial match
+// (one flattened pass over the shortest list of M's constraints, or list
+// length minus bound hits when M has a single constraint list), then the
+// inclusion-exclusion terms over set partitions of the leaves are summed in
+// 128-bit integers.  The 64 lanes hold the 64 partial matches [w0, w0 + 64).
+__device__ void leaf_masks(Ctx& C, uint32_t nb, uint32_t p, bool pv) {
+    const KArgs& a = *C.a;
+    const PlanDesc* P = C.P;
+    const uint32_t lane = C.lane;
+    const uint32_t n_masks = uni(P->n_masks);
+    for (uint32_t mi = 0; mi < n_masks; mi++) {
+        const uint32_t M = uni(P->mask_id[mi]);
+        const LK K = load_lk(P->mdesc[mi], a);
+        uint32_t h = 0;
+        if (K.n_cons == 1 && K.reuse == kNoReuse) {
+            // one list L: |L| minus the bound nodes found in L
+            if (pv) {
+                const DevGraph& g = a.g;
+                const uint32_t nd = C.s.bound[K.lvl(0) * 64 + lane];
+                const uint32_t* off = off_of(g, K.dir(0));
+                const uint32_t o = off[nd], l = off[nd + 1] - o;
+                const uint32_t* L = adj_of(g, K.dir(0)) + o;
+                h = l;
+                for (uint32_t b = 0; b < nb; b++)
+                    if (((K.inj >> b) & 1u) && contains(L, l, C.s.bound[b * 64 + lane])) h -= 1;
+            }
+        } else {
+            const uint32_t len = phase_a<true>(C, K, nb, p, pv, false);
+            const uint32_t incl = scan_incl(len, lane);
+            C.s.incl[lane] = incl;
+            const uint32_t T = uni(__shfl(incl, 63, 64));
+            const bool owns = len > 0;
+            const uint32_t start = incl - len;
+            wave_sync();
+            uint32_t carry = 0;
+            for (uint32_t t0 = 0; t0 < T; t0 += 128) {
+                const uint32_t ga = t0 + lane, gb = t0 + 64 + lane;
+                uint32_t ja, jb;
+                tile_parents(C.s, lane, t0, start, owns, carry, ja, jb);
+                const uint32_t la = ga - (ja ? C.s.incl[ja - 1] : 0u);
+                const uint32_t lb = gb - (jb ? C.s.incl[jb - 1] : 0u);
+                bool oka = ga < T && la < C.s.base_len[ja];
+                bool okb = gb < T && lb < C.s.base_len[jb];
+                uint32_t xa = 0, xb = 0;
+                if (oka) xa = base_elem(C, ja, la, K.reuse);
+                if (okb) xb = base_elem(C, jb, lb, K.reuse);
+                check_pair(C, K, nb, ja, xa, oka, jb, xb, okb);
+                const uint64_t ba = __ballot(oka), bb = __ballot(okb);
+                if (owns) h += own_count(ba, start, len, t0) + own_count(bb, start, len, t0 + 64);
+            }
+            wave_sync();
+        }
+        C.s.hist[lane * 16 + M] = h;
+    }
+    wave_sync();
+    if (pv) {
+        // inclusion-exclusion over set partitions of the leaves
+        const uint32_t* h = C.s.hist + lane * 16;
+        __int128 val = 0;
+        const uint32_t n_terms = uni(P->n_terms);
+        for (uint32_t t = 0; t < n_terms; t++) {
+            const Term& tm = P->terms[t];
+            __int128 prod = tm.coef;
+            for (uint32_t b = 0; b < tm.nb; b++) prod *= (__int128)h[tm.mask[b]];
+            val += prod;
+        }
+        unsigned __int128 v = (unsigned __int128)val;
+        unsigned long long vl = (unsigned long long)v, vh = (unsigned long long)(v >> 64);
+        unsigned long long o = C.acc_lo;
+        C.acc_lo += vl;
+        C.acc_hi += vh + (C.acc_lo < o ? 1ull : 0ull);
+    }
+    wave_sync();
+}
+
 // Count the leaf group for every partial match in level `lv` (= e - 1).
 template <bool NONLIN>
 __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
@@ -594,7 +652,7 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
     const uint32_t nsig = uni(P->n_sig);
     const bool linear = !NONLIN || P->linear != 0;
     const uint32_t nb = lv + 1;  // bound levels 0..lv
-    const LK S0 = load_lk(P->sig[0]);
+    const LK S0 = load_lk(P->sig[0], a);
     for (uint32_t w0 = 0; w0 < nprefix; w0 += 64) {
         const uint32_t p = w0 + lane;
         const bool pv = p < nprefix;
@@ -608,10 +666,11 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
                 if (l > 0) idx = F.parent[idx];
             }
         }
-        if (!linear) {
-            for (int q = 0; q < 16; q++) C.s.hist[lane * 16 + q] = 0;
-        }
         unsigned long long lin = 0;
+        if (!linear) {
+            leaf_masks(C, nb, p, pv);
+            continue;
+        }
         if (linear && S0.n_cons == 1 && S0.reuse == kNoReuse) {
             // one leaf drawn from one list L: |L| minus the bound nodes found in L
             uint32_t v = 0;
@@ -632,9 +691,9 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
             wave_sync();
             continue;
         }
-        for (uint32_t s = 0; s < nsig; s++) {
-            if (!P->sig_scan[s]) continue;
-            const LK S = load_lk(P->sig[s]);
+        {
+            // one leaf signature
+            const LK& S = S0;
             uint32_t len = phase_a<true>(C, S, nb, p, pv, false);
             // one leaf whose set is a base list and one probe list: balanced big
             // pairs leave the flattened pass for the cooperative merge
@@ -655,15 +714,13 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
             }
             uint64_t bigmask = __ballot(big);
             if (big) len = 0;
+            (void)nsig;
             const uint32_t incl = scan_incl(len, lane);
             C.s.incl[lane] = incl;
             const uint32_t T = uni(__shfl(incl, 63, 64));
             const bool owns = len > 0;
             const uint32_t start = incl - len;
             wave_sync();
-            const uint8_t implied = P->sig_implied[s];
-            const uint8_t test = P->sig_test[s];
-            const uint32_t below = (1u << s) - 1u;
             uint32_t carry = 0;
             // two tiles per step
             for (uint32_t t0 = 0; t0 < T; t0 += 128) {
@@ -678,22 +735,8 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
                 if (oka) xa = base_elem(C, ja, la, S.reuse);
                 if (okb) xb = base_elem(C, jb, lb, S.reuse);
                 check_pair(C, S, nb, ja, xa, oka, jb, xb, okb);
-                if (linear) {
-                    // one leaf: survivors are only counted
-                    lin += (unsigned long long)(__popcll(__ballot(oka)) + __popcll(__ballot(okb)));
-                } else {
-                    uint32_t mask_a = implied, mask_b = implied;
-#pragma unroll
-                    for (uint32_t s2 = 0; s2 < (uint32_t)kMaxSig; s2++) {
-                        if (s2 >= nsig || !((test >> s2) & 1u)) continue;
-                        bool ia = oka, ib = okb;
-                        member_pair(C, load_lk(P->sig[s2]), ja, xa, ia, jb, xb, ib);
-                        if (ia) mask_a |= 1u << s2;
-                        if (ib) mask_b |= 1u << s2;
-                    }
-                    if (oka && (mask_a & below) == 0) atomicAdd(&C.s.hist[ja * 16 + mask_a], 1u);
-                    if (okb && (mask_b & below) == 0) atomicAdd(&C.s.hist[jb * 16 + mask_b], 1u);
-                }
+                // one leaf: survivors are only counted
+                lin += (unsigned long long)(__popcll(__ballot(oka)) + __popcll(__ballot(okb)));
             }
             wave_sync();
             // balanced big pairs, one partial match at a time
@@ -715,31 +758,10 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
                 lin += merge_count(C.s, A, blen, B, plen, S.inj, nb, j, lane);
             }
         }
-        if (linear) {
-            if (lane == 0) {
-                unsigned long long o = C.acc_lo;
-                C.acc_lo += lin;
-                if (C.acc_lo < o) C.acc_hi += 1;
-            }
-        } else if (pv) {
-            // superset sums in place: h[m] becomes |intersection of the sets in m|
-            uint32_t* h = C.s.hist + lane * 16;
-            for (uint32_t b = 0; b < nsig; b++)
-                for (uint32_t m = 0; m < 16; m++)
-                    if (!((m >> b) & 1u)) h[m] += h[m | (1u << b)];
-            // inclusion-exclusion over set partitions of the leaves
-            __int128 val = 0;
-            for (uint32_t t = 0; t < P->n_terms; t++) {
-                const Term& tm = P->terms[t];
-                __int128 prod = tm.coef;
-                for (uint32_t b = 0; b < tm.nb; b++) prod *= (__int128)h[tm.mask[b]];
-                val += prod;
-            }
-            unsigned __int128 v = (unsigned __int128)val;
-            unsigned long long vl = (unsigned long long)v, vh = (unsigned long long)(v >> 64);
+        if (lane == 0) {
             unsigned long long o = C.acc_lo;
-            C.acc_lo += vl;
-            C.acc_hi += vh + (C.acc_lo < o ? 1ull : 0ull);
+            C.acc_lo += lin;
+            if (C.acc_lo < o) C.acc_hi += 1;
         }
         wave_sync();
     }
@@ -959,7 +981,8 @@ __global__ void init_kernel(InitArgs a) {
 __global__ void finalize_kernel(KArgs a) {
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < a.n_plans; i += gridDim.x * blockDim.x) {
         int32_t st = 0;
-        if (a.ctl[kCtlQueueFull]) st = -6;
+        if (a.ctl[kCtlBadPlan]) st = -1;
+        else if (a.ctl[kCtlQueueFull]) st = -6;
         else if (a.ctl[kCtlCancelled]) st = -7;
         else if (a.plan_flags[i] & 1u) st = -5;
         a.status[i] = st;

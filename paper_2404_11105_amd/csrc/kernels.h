@@ -23,6 +23,7 @@ enum Ctl : uint32_t {
     kCtlSplitCount = 2,   // split items written by the split kernel
     kCtlCancelled = 3,    // a wave saw the cancel flag
     kCtlQueueFull = 4,    // split queue overflow (cannot happen with a sized workspace)
+    kCtlBadPlan = 5,      // a level had more constraints than the layout holds (cannot happen)
     kCtlWords = 64
 };
 
@@ -35,8 +36,8 @@ struct DevGraph {
     uint32_t n;
     uint32_t row_min;   // lists at least this long have a dense row (kNoRows: none)
     // dense membership rows of long lists: row r is row_words uint32 words at
-    // word offset r * row_words (out rows first, then in rows; < 4 GiB in
-    // all), bit x set iff node x is in the list
+    // word offset r * row_words (out rows first, then in rows; < 16 GiB in
+    // all, so word offsets fit 32 bits), bit x set iff node x is in the list
     const uint32_t* rows;
     const uint2* row_of;  // per node: (out row, in row), 0xFFFFFFFF = no row
     uint32_t row_words;
@@ -46,7 +47,7 @@ struct DevGraph {
 constexpr uint32_t kNoRows = 0xFFFFFFFFu;
 constexpr uint32_t kRowLen = 0xFFFFFFFEu;  // probe-list length marker: test a dense row
 
-constexpr uint64_t kMaxRowBytes = (4ull << 30) - 256;  // rows are addressed by 32-bit byte offsets
+constexpr uint64_t kMaxRowBytes = (16ull << 30) - 256;  // rows are addressed by 32-bit word offsets
 
 // Set the bits of dense rows [0, n_rows): row r holds the out-list (r <
 // n_out_rows) or in-list of node row_node[r].  Rows must be zeroed first.

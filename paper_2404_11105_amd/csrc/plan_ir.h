@@ -34,6 +34,7 @@ constexpr int kMaxSig = 4;        // distinct leaf signatures
 constexpr int kMaxLeaves = 6;     // vertices in the leaf group
 constexpr int kMaxTerms = 96;     // inclusion-exclusion terms after merging
 constexpr int kMaxBlocks = 6;     // blocks in one term
+constexpr int kMaxMasks = 15;     // distinct signature masks the terms use
 constexpr uint8_t kNoReuse = 0xFF;
 
 struct LevelDesc {
@@ -75,6 +76,12 @@ struct PlanDesc {
     uint8_t order[kMaxK];         // level -> pattern vertex (reporting)
     uint8_t pad2[4];
     Term terms[kMaxTerms];
+    // Every signature mask M used by a term block, with the candidate test of
+    // the intersection of those signatures' sets (union of their constraints):
+    // the kernel measures |intersection over s in M of S_s| per partial match.
+    uint32_t n_masks;
+    uint8_t mask_id[16];
+    LevelDesc mdesc[kMaxMasks];
 };
 
 }  // namespace xm

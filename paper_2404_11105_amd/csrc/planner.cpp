@@ -350,6 +350,33 @@ void fill_level(const Pat& p, const std::vector<int>& lvl_of, int v, int nlv_lim
     L.deg_check = (L.dmin_out || L.dmin_in) ? 1 : 0;
 }
 
+// Candidate test of a leaf with in-neighbours `in_mask` and out-neighbours
+// `out_mask` (pattern vertices), all of them bound at levels < nlv_limit.
+void fill_level_sig(const Pat& p, const std::vector<int>& lvl_of, uint32_t in_mask, uint32_t out_mask,
+                    int nlv_limit, LevelDesc& L) {
+    std::memset(&L, 0, sizeof(L));
+    L.reuse = kNoReuse;
+    uint32_t cons_lv = 0;
+    for (int j = 0; j < nlv_limit; j++) {
+        int u = -1;
+        for (int x = 0; x < p.k; x++)
+            if (lvl_of[x] == j) u = x;
+        if (u < 0) continue;
+        if (in_mask & (1u << u)) {  // u -> leaf: leaf in out(phi(u))
+            L.cons_lvl[L.n_cons] = (uint8_t)j;
+            L.cons_dir[L.n_cons++] = 0;
+            cons_lv |= 1u << j;
+        }
+        if (out_mask & (1u << u)) {  // leaf -> u: leaf in in(phi(u))
+            L.cons_lvl[L.n_cons] = (uint8_t)j;
+            L.cons_dir[L.n_cons++] = 1;
+            cons_lv |= 1u << j;
+        }
+    }
+    uint32_t all_lv = (nlv_limit >= 32) ? ~0u : ((1u << nlv_limit) - 1);
+    L.inj = (uint8_t)(all_lv & ~cons_lv);
+}
+
 uint32_t cons_mask_bits(const LevelDesc& L, int c) { return (uint32_t)L.cons_lvl[c] * 2 + L.cons_dir[c]; }
 
 // True (and fills `extra`) when every constraint of src is a constraint of dst.
@@ -460,6 +487,15 @@ std::string plan_json(const Pat& p, const PlanDesc& D, const CoverReport& cr, bo
             s += buf;
         }
         s += "]}";
+    }
+    s += "],\"masks\":[";
+    for (uint32_t i = 0; i < D.n_masks; i++) {
+        if (i) s += ",";
+        std::string o = lvl_json(D.mdesc[i]);
+        o.pop_back();
+        std::snprintf(buf, sizeof buf, ",\"mask\":%u}", D.mask_id[i]);
+        o += buf;
+        s += o;
     }
     s += "],\"arcs\":[";
     for (size_t e = 0; e < p.arcs.size(); e++) s += (e ? "," : "") + arcstr((int)e);
@@ -646,6 +682,27 @@ int build_plan(uint32_t k, uint32_t n_arcs, const uint8_t* arcs, uint32_t flags,
     for (size_t i = 0; i < terms.size(); i++) D.terms[i] = terms[i];
     D.linear = (D.t == 1) ? 1 : 0;
     for (size_t i = 0; i < best.leaves.size(); i++) D.order[D.e + i] = (uint8_t)best.leaves[i];
+    // one candidate test per signature mask the terms use
+    {
+        uint32_t used = 0;
+        for (uint32_t i = 0; i < D.n_terms; i++)
+            for (int b = 0; b < D.terms[i].nb; b++) used |= 1u << D.terms[i].mask[b];
+        D.n_masks = 0;
+        for (uint32_t M = 1; M < 16; M++) {
+            if (!((used >> M) & 1u)) continue;
+            uint32_t in = 0, out = 0;
+            for (uint32_t g = 0; g < D.n_sig; g++)
+                if ((M >> g) & 1u) {
+                    in |= sigs[g].in_mask;
+                    out |= sigs[g].out_mask;
+                }
+            LevelDesc& L = D.mdesc[D.n_masks];
+            fill_level_sig(p, lvl_of, in, out, (int)D.e, L);
+            // a node in every set of M has all of M's arcs to bound nodes
+            if (reduced && D.e >= 2) choose_reuse(D, L, (int)D.e - 1, (uint32_t)popc(out), (uint32_t)popc(in));
+            D.mask_id[D.n_masks++] = (uint8_t)M;
+        }
+    }
     // packed constraint fields read by the kernel
     auto pack = [](LevelDesc& L) {
         L.dir_mask = 0;
@@ -657,6 +714,7 @@ int build_plan(uint32_t k, uint32_t n_arcs, const uint8_t* arcs, uint32_t flags,
     };
     for (uint32_t i = 1; i < D.e; i++) pack(D.lvl[i]);
     for (uint32_t g = 0; g < D.n_sig; g++) pack(D.sig[g]);
+    for (uint32_t i = 0; i < D.n_masks; i++) pack(D.mdesc[i]);
     json = plan_json(p, D, cr, reduced, best.cost);
     return 0;
 }

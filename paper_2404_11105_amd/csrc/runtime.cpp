@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <functional>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -133,6 +134,8 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
         L.e_max = std::max(L.e_max, D.e);
         for (uint32_t l = 1; l < D.e; l++) L.maxc = std::max<uint32_t>(L.maxc, D.lvl[l].n_cons);
         for (uint32_t s = 0; s < D.n_sig; s++) L.maxc = std::max<uint32_t>(L.maxc, D.sig[s].n_cons);
+        // a signature mask unites the constraints of several signatures
+        for (uint32_t i = 0; i < D.n_masks; i++) L.maxc = std::max<uint32_t>(L.maxc, D.mdesc[i].n_cons);
         if (!D.linear) L.nonlinear = true;
         if (D.e >= 2) splittable++;
     }
@@ -531,19 +534,30 @@ int xm_graph_dense_rows(xm_graph_t* g, uint64_t max_bytes, uint32_t min_len, voi
     max_bytes = std::min<uint64_t>(max_bytes, xm::kMaxRowBytes);
     const uint64_t words = ((uint64_t)g->n + 31) / 32;
     const uint64_t row_bytes = words * 4;
-    // the smallest threshold (doubling from min_len, at least 32) whose rows fit
-    uint64_t t = std::max<uint32_t>(min_len, 32);
-    const uint32_t longest = std::max(g->max_out, g->max_in);
-    uint64_t n_out = 0, n_in = 0;
-    for (; t <= longest; t *= 2) {
-        n_out = n_in = 0;
-        for (const uint2& d : g->hdeg) {
-            n_out += d.x >= t;
-            n_in += d.y >= t;
-        }
-        if ((n_out + n_in) * row_bytes <= max_bytes) break;
+    // rows go to the longest lists first: the threshold is the smallest list
+    // length (at least max(min_len, 32)) such that every list at least that
+    // long, in both directions, has a row within max_bytes
+    const uint64_t fit = max_bytes / row_bytes;
+    const uint32_t lo = std::max<uint32_t>(min_len, 32);
+    std::vector<uint32_t> lens;
+    for (const uint2& d : g->hdeg) {
+        if (d.x >= lo) lens.push_back(d.x);
+        if (d.y >= lo) lens.push_back(d.y);
     }
-    if (t > longest || n_out + n_in == 0) return XM_OK;
+    if (lens.empty() || fit == 0) return XM_OK;
+    std::sort(lens.begin(), lens.end(), std::greater<uint32_t>());
+    uint64_t t = lo;
+    if (lens.size() > fit) {
+        // lens[fit] must stay below the threshold (ties included)
+        t = (uint64_t)lens[fit] + 1;
+        if (t > lens[0]) return XM_OK;
+    }
+    uint64_t n_out = 0, n_in = 0;
+    for (const uint2& d : g->hdeg) {
+        n_out += d.x >= t;
+        n_in += d.y >= t;
+    }
+    if (n_out + n_in == 0) return XM_OK;
     std::vector<uint2> row_of(g->n, make_uint2(0xFFFFFFFFu, 0xFFFFFFFFu));
     std::vector<uint32_t> row_node;
     row_node.reserve(n_out + n_in);

@@ -198,27 +198,24 @@ class Model:
                     self.total += (hi - lo) - sum(1 for b in range(lv + 1)
                                                   if (S0["inj"] >> b) & 1 and bound[b] in L)
                     continue
+                # several signatures: h[M] = |intersection of the sets in M| for
+                # every mask the terms use, then the inclusion-exclusion terms
                 hist = [0] * 16
-                for s, S in enumerate(sigs):
-                    if not S["scan"]:
+                for M in P["masks"]:
+                    if len(M["cons"]) == 1 and M["reuse"] < 0:
+                        j, d = M["cons"][0]
+                        L = self.sets[d][bound[j]]
+                        lo, hi = self._rng(bound[j], d)
+                        hist[M["mask"]] = (hi - lo) - sum(1 for b in range(lv + 1)
+                                                          if (M["inj"] >> b) & 1 and bound[b] in L)
                         continue
-                    m = self.phase_a(S, lv + 1, p, True, bound, anc)
+                    m = self.phase_a(M, lv + 1, p, True, bound, anc)
+                    cnt = 0
                     for local in range(m["len"]):
-                        x = self.base_elem(m, local, S["reuse"])
-                        if not self.check(S, lv + 1, bound, m, x):
-                            continue
-                        mask = S["implied"]
-                        for s2 in range(nsig):
-                            if (S["test"] >> s2) & 1:
-                                S2 = sigs[s2]
-                                if all(x in self.sets[d][bound[j]] for j, d in S2["cons"]):
-                                    mask |= 1 << s2
-                        if mask & ((1 << s) - 1) == 0:
-                            hist[mask] += 1
-                for b in range(nsig):
-                    for mm in range(16):
-                        if not (mm >> b) & 1:
-                            hist[mm] += hist[mm | (1 << b)]
+                        x = self.base_elem(m, local, M["reuse"])
+                        if self.check(M, lv + 1, bound, m, x):
+                            cnt += 1
+                    hist[M["mask"]] = cnt
                 val = 0
                 for t in P["terms"]:
                     prod = t["coef"]
