@@ -896,9 +896,12 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
             C.pi = uni(item % a.n_plans);
             C.P = a.plans + C.pi;
             const uint32_t ci = item / a.n_plans;
-            const uint32_t first = ci * a.chunk;
-            const uint32_t idx = first + C.lane;
-            bool ok = C.lane < a.chunk && idx < a.n_src;
+            // chunk ci takes the roots ci, ci + chunks, ci + 2 chunks, ...: long
+            // lists cluster at low ids on power-law generators, and striding
+            // spreads them over many tasks
+            const uint64_t idx64 = (uint64_t)ci + (uint64_t)C.lane * chunks_per_plan;
+            const uint32_t idx = (uint32_t)(idx64 < a.n_src ? idx64 : a.n_src);
+            bool ok = C.lane < a.chunk && idx64 < a.n_src;
             uint32_t r = 0;
             if (ok) {
                 r = a.roots ? a.roots[idx] : idx;

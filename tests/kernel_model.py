@@ -269,9 +269,11 @@ class Model:
         for r, lo, hi in items:
             F0["node"][0], F0["parent"][0], F0["aux"][0] = r, lo, hi
             self.explore(1)
-        for c0 in range(0, g.n, self.chunk):
+        n_chunks = -(-g.n // self.chunk)
+        for c0 in range(n_chunks):
             n0 = 0
-            for r in range(c0, min(g.n, c0 + self.chunk)):
+            # chunk c0 takes the roots c0, c0 + n_chunks, ... (strided)
+            for r in range(c0, g.n, n_chunks)[: self.chunk]:
                 do, di = self.deg(r)
                 if do < rdo or di < rdi:
                     continue
