@@ -41,41 +41,52 @@ def lib_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def timed_steps(counter, stream, steps, warmup):
+def timed_steps(counter, stream, steps, warmup, progress=None):
     """Wall time per step, and the GPU time of each launch from HIP events
     recorded on the launch stream around it (these also cover the three
-    microsecond-scale set-up/status kernels next to the count kernel)."""
+    microsecond-scale set-up/status kernels next to the count kernel).
+    progress(msg), if given, is called after every launch."""
     import torch
-    for _ in range(warmup):
+    for i in range(warmup):
         counter.run(stream)
+        stream.synchronize()
+        if progress:
+            progress(f"  warm-up launch {i} done")
     stream.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for e0, e1 in evs:
+    for i, (e0, e1) in enumerate(evs):
         e0.record(stream)
         counter.run(stream)
         e1.record(stream)
         stream.synchronize()
+        if progress:
+            progress(f"  step {i}: {e0.elapsed_time(e1):.1f} ms")
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps * 1e3
     gpu = sum(e0.elapsed_time(e1) for e0, e1 in evs) / steps
     return wall, gpu
 
 
-def timed_plain(counters, stream, steps, warmup):
+def timed_plain(counters, stream, steps, warmup, progress=None):
     import torch
     for _ in range(warmup):
         for c in counters:
             c.run(stream)
+        stream.synchronize()
+        if progress:
+            progress("  plain warm-up done")
     stream.synchronize()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for i in range(steps):
         for c in counters:
             c.run(stream)
         stream.synchronize()
+        if progress:
+            progress(f"  plain step {i} done")
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps * 1e3
 
@@ -159,11 +170,13 @@ def bench_batch256(args):
     plans = [Plan(p, reduced=True, graph=G) for p in pats]
     s = torch.cuda.Stream()
     log("[batch] autotuning")
-    opts, trec = tune(G, plans, stream=s, reps=1, budget_s=150, log=log)
+    log(f"[batch] dense rows {G.dense_rows_info()}")
+    opts, trec = tune(G, plans, stream=s, reps=1, budget_s=120, log=log)
     log(f"[batch] tuned {opts} ({trec['ms']:.1f} ms vs default {trec['default_ms']:.1f} ms)")
     cb = Counter(G, plans, **opts)
     cb.capture(s)
-    ms_b, gpu_b = timed_steps(cb, s, args.steps, args.warmup)
+    log("[batch] batched launches (HIP graph)")
+    ms_b, gpu_b = timed_steps(cb, s, args.steps, args.warmup, progress=log)
     counts, status = cb.results()
     assert all(x == 0 for x in status), status
     log("[batch] 256 plain launches")
@@ -171,7 +184,7 @@ def bench_batch256(args):
                      device="cuda")
     plain = [Counter(G, [p], workspace=ws, **opts) for p in plans]
     steps_plain = max(1, args.steps // 2)
-    ms_p = timed_plain(plain, s, steps_plain, 1)
+    ms_p = timed_plain(plain, s, steps_plain, 1, progress=log)
     plain_counts = [c.results()[0][0] for c in plain]
     assert plain_counts == counts, "batched and plain counts differ"
     # oracle parity on root subsets of a sample of patterns
@@ -198,7 +211,7 @@ def bench_batch256(args):
         "config": {"workload": "batch256_rmat22", "n": g.n, "m": g.m, "patterns": len(pats),
                    "pattern_sizes": {k: sum(1 for p in pats if p.k == k) for k in (3, 4, 5, 6)},
                    "plan": "reduced", "launch": "one persistent launch, HIP graph, autotuned",
-                   "tuned": opts},
+                   "tuned": opts, "dense_rows": G.dense_rows_info()},
         "batched_gpu_ms": round(gpu_b, 3), "plain_ms_per_step": round(ms_p, 3),
         "batched_vs_plain_speedup": round(ms_p / ms_b, 3),
         "tune": trec, "counts_sum": str(total), "batched_equals_plain": True,
