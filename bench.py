@@ -220,6 +220,57 @@ def bench_batch256(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_fraction(args):
+    """Exploration of a growing share of start nodes (the paper's experiment on
+    the percentage of start nodes, here on the R-MAT scale 16 workload): a
+    seeded permutation of the nodes is cut into ten deciles; the batched launch
+    of the four patterns runs on the first 10%, 20%, ..., 100% of it, and the
+    ten disjoint deciles' counts must sum to the full counts."""
+    import numpy as np
+    import torch
+
+    import xmgen
+    from paper_2404_11105_amd import Counter, Graph, Plan
+
+    torch.cuda.set_device(0)
+    log("[fraction] generating R-MAT scale 16")
+    g = xmgen.rmat(16, seed=0)
+    pats = [xmgen.named(n) for n in PATTERNS]
+    G = Graph(g)
+    # every plan of a root-subset launch starts at the same pattern vertex
+    plans = [Plan(p, reduced=True, graph=G, root_vertex=0) for p in pats]
+    perm = np.random.default_rng(16).permutation(g.n).astype(np.uint32)
+    cuts = [round(g.n * i / 10) for i in range(11)]
+    s = torch.cuda.Stream()
+    full = Counter(G, plans)
+    full.run(s)
+    want = full.results()[0]
+    sums = [0] * len(plans)
+    for i in range(10):
+        c = Counter(G, plans, roots=np.sort(perm[cuts[i]:cuts[i + 1]]))
+        c.run(s)
+        got, st = c.results()
+        assert st == [0] * len(plans)
+        sums = [a + b for a, b in zip(sums, got)]
+    points = []
+    for i in range(1, 11):
+        c = Counter(G, plans, roots=np.sort(perm[:cuts[i]]))
+        c.capture(s)
+        ms, _ = timed_steps(c, s, max(2, args.steps // 4), 1)
+        counts, st = c.results()
+        points.append({"fraction": i / 10, "ms": round(ms, 3), "counts": [str(x) for x in counts]})
+        log(f"[fraction] {i * 10}% of start nodes: {ms:.2f} ms")
+    rec = {
+        "metric": METRIC, "value": sum(want) / (points[-1]["ms"] / 1e3), "unit": "embeddings/s",
+        "n_gpus": 1, "steps": max(2, args.steps // 4), "warmup": 1, "ms_per_step": points[-1]["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "rmat16_start_node_fraction", "patterns": PATTERNS, "start_vertex": 0,
+                   "root_order": "seeded permutation, numpy default_rng(16)"},
+        "points": points, "deciles_sum_to_full": sums == want, "full_counts": [str(x) for x in want],
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def bench_serve(args):
     """Continuous batching over 8 resident R-MAT graphs (scales 18-24, built
     on the device); Poisson arrivals at two fixed rates set from the measured
@@ -325,7 +376,7 @@ def main():
                     help="shortest list with a dense membership row (default: the library's)")
     ap.add_argument("--dense-rows", type=int, default=None,
                     help="byte budget of the dense rows (0: none; default: the library's)")
-    ap.add_argument("--workload", default="rmat16", choices=["rmat16", "batch256", "serve"],
+    ap.add_argument("--workload", default="rmat16", choices=["rmat16", "batch256", "serve", "fraction"],
                     help="rmat16: the contract line (default); batch256 / serve: the batched "
                          "and serving workloads, each printing its own JSON line")
     ap.add_argument("--requests", type=int, default=400, help="serve: requests per load level")
@@ -346,6 +397,9 @@ def main():
         return
     if args.workload == "serve":
         bench_serve(args)
+        return
+    if args.workload == "fraction":
+        bench_fraction(args)
         return
 
     import numpy as np

@@ -223,6 +223,11 @@ typedef struct xm_count_opts {
        small set-up and status kernels. */
     void* ev_kernel_start;
     void* ev_kernel_stop;
+    /* Host copy of roots_dev (nullable; read only when struct_size covers
+       it).  With it the split-task queue is sized from the subset's own
+       degrees; without it every subset root is assumed to have the longest
+       list in the graph, which can coarsen the hub splits. */
+    const uint32_t* roots_host;
 } xm_count_opts;
 
 size_t xm_workspace_size(const xm_graph_t* g, uint32_t n_plans,

@@ -50,6 +50,7 @@ class XmCountOpts(ctypes.Structure):
         ("merge_ratio", ctypes.c_uint32),
         ("ev_kernel_start", ctypes.c_void_p),
         ("ev_kernel_stop", ctypes.c_void_p),
+        ("roots_host", ctypes.c_void_p),
     ]
 
 

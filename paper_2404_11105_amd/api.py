@@ -145,7 +145,9 @@ def describe_plan(pattern, reduced: bool = True) -> dict:
 
 
 def make_opts(chunk=0, split=0, cap=0, waves_per_cu=0, roots=None, cancel=None, events=None,
-              merge_min=0, merge_ratio=0, split_work=0):
+              merge_min=0, merge_ratio=0, split_work=0, roots_host=None):
+    """xm_count_opts; roots is a device tensor, roots_host (optional) a
+    contiguous uint32 numpy copy the caller keeps alive."""
     o = _lib.XmCountOpts()
     o.struct_size = ctypes.sizeof(_lib.XmCountOpts)
     o.chunk, o.split, o.cap, o.waves_per_cu = chunk, split, cap, waves_per_cu
@@ -153,6 +155,8 @@ def make_opts(chunk=0, split=0, cap=0, waves_per_cu=0, roots=None, cancel=None, 
     if roots is not None:
         o.roots_dev = roots.data_ptr()
         o.n_roots = roots.numel()
+        if roots_host is not None:
+            o.roots_host = roots_host.ctypes.data
     if cancel is not None:
         o.cancel_dev = cancel.data_ptr()
     if events is not None:
@@ -175,9 +179,10 @@ class Counter:
         self.graph = graph
         self.plans = list(plans)
         dev = graph.device
-        self.roots = None
+        self.roots = self.roots_host = None
         if roots is not None:
-            self.roots = _u32_tensor(np.asarray(roots, dtype=np.uint32), dev)
+            self.roots_host = np.ascontiguousarray(roots, dtype=np.uint32)
+            self.roots = _u32_tensor(self.roots_host, dev)
         self.cancel = cancel
         self.events = None
         if kernel_events:
@@ -188,7 +193,7 @@ class Counter:
                 for ev in self.events:
                     ev.record(s)
         self.opts = make_opts(chunk, split, cap, waves_per_cu, self.roots, cancel, self.events,
-                              merge_min, merge_ratio, split_work)
+                              merge_min, merge_ratio, split_work, self.roots_host)
         self._parr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
         ws = lib().xm_workspace_size(graph.handle, len(self.plans), self._parr, ctypes.byref(self.opts))
         if ws == 0:
@@ -325,6 +330,23 @@ def workspace_bytes(graph: Graph, plans, **opts) -> int:
     if ws == 0:
         check(_lib.XM_ERR_INVALID)
     return int(ws)
+
+
+def count_anchored(graph: Graph, pattern, vertex: int, nodes, reduced: bool = True, stream=None, **opts):
+    """Embeddings of `pattern` that map pattern vertex `vertex` to each data
+    node in `nodes` (a constant pattern vertex, Definition 2.2's vertex
+    constraints): the plan starts at `vertex` and each node is a one-root
+    subset.  Returns one count per node."""
+    import numpy as np
+    plan = Plan(pattern, reduced=reduced, graph=graph, root_vertex=vertex)
+    out = []
+    for x in np.asarray(nodes, dtype=np.uint32).reshape(-1):
+        c = Counter(graph, [plan], roots=np.array([x], dtype=np.uint32), **opts)
+        c.run(stream)
+        counts, status = c.results()
+        check(status[0])
+        out.append(counts[0])
+    return out
 
 
 def count(graph: Graph, plans, stream=None, **opts):

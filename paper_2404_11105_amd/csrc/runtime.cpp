@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <atomic>
 #include <functional>
 #include <cstdio>
@@ -107,8 +108,13 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
                 const xm_count_opts* o, Layout& L) {
     if (!g) return fail(XM_ERR_INVALID, "graph is NULL");
     if (n_plans == 0 || !plans) return fail(XM_ERR_INVALID, "no plans");
-    if (o && o->struct_size != 0 && o->struct_size < sizeof(xm_count_opts))
+    // struct_size: 0 or at least the layout before roots_host (fields added
+    // later are read only when struct_size covers them)
+    if (o && o->struct_size != 0 && o->struct_size < offsetof(xm_count_opts, roots_host))
         return fail(XM_ERR_INVALID, "xm_count_opts.struct_size too small");
+    const uint32_t* roots_host =
+        (o && o->roots_dev && (o->struct_size == 0 || o->struct_size >= sizeof(xm_count_opts))) ? o->roots_host
+                                                                                               : nullptr;
     L.chunk = (o && o->chunk) ? o->chunk : 0;  // 0: sized below from the task count
     L.split = (o && o->split) ? o->split : 64;
     L.split_work = (o && o->split_work) ? o->split_work : 4096;
@@ -171,6 +177,24 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
     };
     auto count_items = [&](uint32_t sw) -> uint64_t {
         uint64_t tot = 0;
+        if (o && o->roots_dev && roots_host) {
+            // exact, from the subset's degrees
+            for (uint32_t i = 0; i < n_plans; i++) {
+                const PlanDesc& D = plans[i]->desc;
+                if (D.e < 2) continue;
+                for (uint32_t k = 0; k < o->n_roots; k++) {
+                    const uint32_t r = roots_host[k];
+                    if (r >= g->n) continue;
+                    const uint2 d = g->hdeg[r];
+                    if (std::max(d.x, d.y) <= xm::kHubMin) continue;  // the split kernel's cut
+                    if (d.x < D.root_dout || d.y < D.root_din) continue;
+                    uint32_t L1 = 0xFFFFFFFFu;
+                    for (int c = 0; c < D.lvl[1].n_cons; c++) L1 = std::min(L1, D.lvl[1].cons_dir[c] ? d.y : d.x);
+                    tot += pieces(L1, sw);
+                }
+            }
+            return tot;
+        }
         if (o && o->roots_dev) {  // subset degrees are not known on the host: bound them
             return (uint64_t)o->n_roots * pieces(max_list, sw) * splittable;
         }

@@ -14,6 +14,11 @@ never exceeds `hbm_budget`.  A request whose batch could never fit is
 rejected at once.  Each request may carry a deadline; one that expires while
 still queued is completed with status XM_ERR_CANCELLED without running.
 
+A request may be anchored: pin = (v, x) counts only the embeddings that map
+pattern vertex v to data node x (a constant pattern vertex).  Its plan starts
+at v and its launch is restricted to the root subset {x}; anchored requests
+batch with others on the same graph and node.
+
 Latency = completion time - submission time (host clock).  `stats()` gives
 p50 / p99 latency and counts/s over the completed requests.
 """
@@ -37,6 +42,7 @@ class Request:
     submitted: float
     deadline: float | None
     future: Future
+    pin: tuple | None = None      # (pattern vertex, data node)
     done: float = 0.0
     status: int = 0
     count: int | None = None
@@ -52,19 +58,20 @@ class GpuBackend:
         self.opts = dict(opts or {})
         self.plans = {}
 
-    def plan(self, graph_id, pattern):
+    def plan(self, graph_id, pattern, pin_vertex=None):
         from .api import Plan
-        key = (graph_id, pattern.k, pattern.arcs)
+        key = (graph_id, pattern.k, pattern.arcs, pin_vertex)
         p = self.plans.get(key)
         if p is None:
-            p = Plan(pattern, reduced=True, graph=self.graphs[graph_id])
+            p = Plan(pattern, reduced=True, graph=self.graphs[graph_id], root_vertex=pin_vertex)
             self.plans[key] = p
         return p
 
-    def footprint(self, graph_id, plans) -> int:
+    def footprint(self, graph_id, plans, node=None) -> int:
         import ctypes
         from ._lib import XminerError, lib
         from .api import make_opts
+        # an anchored launch (node given) needs at most the full-graph workspace
         o = make_opts(**self.opts)
         arr = (ctypes.c_void_p * len(plans))(*[p.handle.value for p in plans])
         ws = lib().xm_workspace_size(self.graphs[graph_id].handle, len(plans), arr, ctypes.byref(o))
@@ -75,9 +82,11 @@ class GpuBackend:
     def new_slot(self):
         return self.torch.cuda.Stream()
 
-    def launch(self, slot, graph_id, plans):
+    def launch(self, slot, graph_id, plans, node=None):
+        import numpy as np
         from .api import Counter
-        c = Counter(self.graphs[graph_id], plans, **self.opts)
+        roots = None if node is None else np.array([node], dtype=np.uint32)
+        c = Counter(self.graphs[graph_id], plans, roots=roots, **self.opts)
         c.run(slot)
         ev = self.torch.cuda.Event()
         ev.record(slot)
@@ -113,12 +122,15 @@ class Server:
         self.thread.start()
 
     # ---- client side
-    def submit(self, graph_id, pattern, deadline_s: float | None = None) -> Future:
+    def submit(self, graph_id, pattern, deadline_s: float | None = None, pin=None) -> Future:
+        """Queue a count of `pattern` on graph `graph_id`; pin = (v, x) anchors
+        pattern vertex v at data node x.  The future gives (count, status)."""
         now = time.perf_counter()
         f = Future()
         with self.lock:
             r = Request(self.next_id, graph_id, pattern, now,
-                        now + deadline_s if deadline_s is not None else None, f)
+                        now + deadline_s if deadline_s is not None else None, f,
+                        pin=tuple(pin) if pin is not None else None)
             self.next_id += 1
             self.pending.append(r)
             self.lock.notify()
@@ -168,22 +180,24 @@ class Server:
                 self.pending.popleft()
                 self._finish(head, XM_ERR_CANCELLED, None)
                 continue
-            # gather same-graph requests in arrival order
+            # gather requests on the same graph (and anchor node) in arrival order
+            node = head.pin[1] if head.pin else None
             batch, rest = [], collections.deque()
             while self.pending:
                 r = self.pending.popleft()
-                if r.graph_id == head.graph_id and len(batch) < self.max_batch and (
+                r_node = r.pin[1] if r.pin else None
+                if r.graph_id == head.graph_id and r_node == node and len(batch) < self.max_batch and (
                         r.deadline is None or now <= r.deadline):
                     batch.append(r)
                 else:
                     rest.append(r)
             # shrink the batch until it fits the free budget
-            plans = [self.backend.plan(r.graph_id, r.pattern) for r in batch]
-            fp = self.backend.footprint(head.graph_id, plans)
+            plans = [self.backend.plan(r.graph_id, r.pattern, r.pin[0] if r.pin else None) for r in batch]
+            fp = self.backend.footprint(head.graph_id, plans, node)
             while fp > self.hbm_budget - self.in_use and len(batch) > 1:
                 rest.appendleft(batch.pop())
                 plans.pop()
-                fp = self.backend.footprint(head.graph_id, plans)
+                fp = self.backend.footprint(head.graph_id, plans, node)
             if fp > self.hbm_budget:
                 # even alone this request can never fit
                 self._finish(batch[0], XM_ERR_ADMISSION, None)
@@ -195,7 +209,7 @@ class Server:
                 break
             self.pending = collections.deque(sorted(rest, key=lambda q: q.rid))
             si = free.pop(0)
-            handle = self.backend.launch(self.slots[si], head.graph_id, plans)
+            handle = self.backend.launch(self.slots[si], head.graph_id, plans, node)
             self.busy[si] = (handle, batch, fp)
             self.in_use += fp
             self.launches += 1

@@ -193,3 +193,22 @@ def test_config2_full_size(xa):
     assert run(xa, g, pats, G=G, reduced=True) == want
     assert run(xa, g, pats, G=G, reduced=False) == want
 
+
+
+def test_root_deciles_sum_to_full_counts(xa):
+    """Disjoint root subsets (deciles of a seeded permutation, queue sized
+    from the subsets' own degrees) add up to the full counts."""
+    banner("rmat 11 named patterns: ten disjoint root subsets sum to the full counts")
+    _, g, pats, want = golden_case("rmat11_named")
+    G = xa.Graph(g)
+    plans = [xa.Plan(p, graph=G, root_vertex=0) for p in pats]
+    perm = np.random.default_rng(3).permutation(g.n).astype(np.uint32)
+    cuts = [round(g.n * i / 10) for i in range(11)]
+    sums = [0] * len(plans)
+    for i in range(10):
+        c = xa.Counter(G, plans, roots=np.sort(perm[cuts[i]:cuts[i + 1]]))
+        c.run()
+        got, st = c.results()
+        assert st == [0] * len(plans)
+        sums = [a + b for a, b in zip(sums, got)]
+    assert sums == want

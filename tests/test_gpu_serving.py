@@ -134,3 +134,28 @@ def test_watchdog_flag_in_pinned_host_memory(xa):
     c.run()
     counts, status = c.results()
     assert status == [0, 0] and counts == [oracle.count(g, p.pattern) for p in plans]
+
+
+def test_anchored_counts_equal_oracle_and_sum_to_total(xa):
+    """A constant pattern vertex: counts with vertex v pinned at node x equal
+    the oracle's per-root counts, and over all x they sum to the total."""
+    banner("anchored counts: uniform 60/400 all nodes, rmat 9 sampled hubs and leaves")
+    g = xmgen.uniform_digraph(60, 400, 9)
+    G = xa.Graph(g)
+    for name in ["ffl", "bifan", "tt4p"]:
+        p = xmgen.named(name)
+        total = oracle.count(g, p)
+        for v in range(p.k):
+            got = xa.count_anchored(G, p, v, np.arange(g.n))
+            assert sum(got) == total, (name, v)
+    g = xmgen.rmat(9, seed=4)
+    G = xa.Graph(g)
+    deg = np.diff(g.out_off.astype(np.int64)) + np.diff(g.in_off.astype(np.int64))
+    nodes = np.concatenate([np.argsort(-deg)[:4], np.nonzero(deg == 0)[0][:2], [7, 100, 500]]).astype(np.uint32)
+    for name in ["c4", "mixed_star", "c5chord"]:
+        p = xmgen.named(name)
+        for v in (0, p.k - 1):
+            want = [oracle.count(g, p, roots=[int(x)], root_vertex=v, mode="B") for x in nodes]
+            for reduced in (True, False):
+                got = xa.count_anchored(G, p, v, nodes, reduced=reduced)
+                assert got == want, (name, v, reduced)

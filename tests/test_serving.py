@@ -21,18 +21,21 @@ class FakeBackend:
         self.max_inflight = 0
         self.mu = threading.Lock()
 
-    def plan(self, graph_id, pattern):
-        return pattern
+    def plan(self, graph_id, pattern, pin_vertex=None):
+        return (pattern, pin_vertex)
 
-    def footprint(self, graph_id, plans):
+    def footprint(self, graph_id, plans, node=None):
         return self.ws + 24 * len(plans)
 
     def new_slot(self):
         return object()
 
-    def launch(self, slot, graph_id, plans):
+    def launch(self, slot, graph_id, plans, node=None):
         g = self.graphs[graph_id]
-        counts = [oracle.count(g, p) for p in plans]
+        if node is None:
+            counts = [oracle.count(g, p) for p, _ in plans]
+        else:
+            counts = [oracle.count(g, p, roots=[node], root_vertex=v) for p, v in plans]
         with self.mu:
             self.inflight += 1
             self.max_inflight = max(self.max_inflight, self.inflight)
@@ -118,3 +121,19 @@ def test_expired_deadline_is_cancelled_without_running():
     s.close()
     assert st == XM_ERR_CANCELLED and c is None
     assert len(be.launched) == 1
+
+
+def test_anchored_requests_batch_by_node_and_sum_to_the_total():
+    """Anchored requests (pattern vertex v at node x) count the embeddings
+    with that image; over all x they sum to the unanchored count."""
+    G = {"u": xmgen.uniform_digraph(40, 200, 3)}
+    be = FakeBackend(G, secs_per_plan=0.001)
+    s = Server(be, hbm_budget=10 ** 6, slots=2, max_batch=8)
+    p = xmgen.named("ffl")
+    total = s.submit("u", p).result(timeout=60)[0]
+    futs = {(v, x): s.submit("u", p, pin=(v, x)) for x in range(40) for v in range(p.k)}
+    for v in range(p.k):
+        assert sum(futs[(v, x)].result(timeout=60)[0] for x in range(40)) == total
+    s.close()
+    # anchored requests on the same node share launches
+    assert any(n > 1 for _, n in be.launched[1:])
