@@ -314,27 +314,28 @@ def bench_serve(args):
         qps = frac * cap_rps
         reqs = draw(args.requests)
         gaps = rng.exponential(1.0 / qps, size=len(reqs))
-        log(f"[serve] {len(reqs)} requests at {qps:.1f}/s")
-        srv = Server(backend, budget, slots=4, max_batch=16)
-        futs = []
-        t_next = time.perf_counter()
-        for (gid, p), gap in zip(reqs, gaps):
-            t_next += gap
-            d = t_next - time.perf_counter()
-            if d > 0:
-                time.sleep(d)
-            futs.append(srv.submit(gid, p))
-            if len(futs) % 50 == 0:
-                log(f"[serve]   submitted {len(futs)}")
-        res = []
-        for f in futs:
-            res.append(f.result())
-            if len(res) % 50 == 0:
-                log(f"[serve]   completed {len(res)}")
-        srv.close()
-        st = srv.stats()
-        st.update(qps=qps, load=frac)
-        levels.append((st, reqs, res))
+        for policy in ("fifo", "sjf"):
+            log(f"[serve] {len(reqs)} requests at {qps:.1f}/s, policy {policy}")
+            srv = Server(backend, budget, slots=4, max_batch=16, policy=policy)
+            futs = []
+            t_next = time.perf_counter()
+            for (gid, p), gap in zip(reqs, gaps):
+                t_next += gap
+                d = t_next - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                futs.append(srv.submit(gid, p))
+                if len(futs) % 50 == 0:
+                    log(f"[serve]   submitted {len(futs)}")
+            res = []
+            for f in futs:
+                res.append(f.result())
+                if len(res) % 50 == 0:
+                    log(f"[serve]   completed {len(res)}")
+            srv.close()
+            st = srv.stats()
+            st.update(qps=qps, load=frac, policy=policy)
+            levels.append((st, reqs, res))
     # alone vs in the mix, on a sample of the last level's requests
     log("[serve] alone vs mix")
     st_last, reqs, res = levels[-1]
@@ -352,7 +353,8 @@ def bench_serve(args):
         "data": "synthetic",
         "config": {"workload": "serve_rmat18-24x8", "graph_scales": scales,
                    "resident_bytes": resident, "pattern_pool": len(pool),
-                   "arrivals": "Poisson", "hbm_budget_bytes": budget, "slots": 4, "max_batch": 16},
+                   "arrivals": "Poisson", "hbm_budget_bytes": budget, "slots": 4, "max_batch": 16,
+                   "policies": ["fifo", "sjf"]},
         "capacity_requests_per_s": cap_rps,
         "levels": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in l[0].items()}
                    for l in levels],
@@ -379,7 +381,7 @@ def main():
     ap.add_argument("--workload", default="rmat16", choices=["rmat16", "batch256", "serve", "fraction"],
                     help="rmat16: the contract line (default); batch256 / serve: the batched "
                          "and serving workloads, each printing its own JSON line")
-    ap.add_argument("--requests", type=int, default=400, help="serve: requests per load level")
+    ap.add_argument("--requests", type=int, default=150, help="serve: requests per load level and policy")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run plain device copies of this size (counter calibration)")
     args = ap.parse_args()

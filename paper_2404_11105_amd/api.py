@@ -210,6 +210,28 @@ class Counter:
         self.counts = torch.zeros(2 * len(self.plans), dtype=torch.int64, device=dev)
         self.status = torch.zeros(len(self.plans), dtype=torch.int32, device=dev)
         self.exec = None
+        # the fills and copies above run on torch's current stream; a launch on
+        # another stream must wait for them
+        self._ready = torch.cuda.Event()
+        self._ready.record(torch.cuda.current_stream(dev))
+        self._streams = set()
+
+    def _order(self, stream):
+        """Make `stream` wait for this object's set-up, and tell torch's
+        allocator that its buffers are used there."""
+        import torch
+        if stream is None:
+            return
+        cur = torch.cuda.current_stream(self.graph.device)
+        if stream == cur:
+            return
+        stream.wait_event(self._ready)
+        key = stream.cuda_stream
+        if key not in self._streams:
+            self._streams.add(key)
+            for t in (self.workspace, self.counts, self.status, self.roots):
+                if t is not None:
+                    t.record_stream(stream)
 
     def _args(self):
         return (self.graph.handle, len(self.plans), self._parr, ctypes.byref(self.opts),
@@ -219,6 +241,7 @@ class Counter:
     def run(self, stream=None):
         import torch
         with torch.cuda.device(self.graph.device):
+            self._order(stream)
             if self.exec is not None:
                 check(lib().xm_exec_launch(self.exec, _stream_ptr(stream)))
             else:
@@ -229,6 +252,9 @@ class Counter:
         import torch
         h = ctypes.c_void_p()
         with torch.cuda.device(self.graph.device):
+            # set-up must be complete before the recorded launches read it
+            self._ready.synchronize()
+            self._order(stream)
             check(lib().xm_count_capture(*self._args(), _stream_ptr(stream), ctypes.byref(h)))
         self.exec = h
 

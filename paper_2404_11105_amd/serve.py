@@ -19,6 +19,12 @@ pattern vertex v to data node x (a constant pattern vertex).  Its plan starts
 at v and its launch is restricted to the root subset {x}; anchored requests
 batch with others on the same graph and node.
 
+Order: policy "fifo" takes the oldest pending request first; policy "sjf"
+takes the request with the smallest estimated cost first (the backend's
+estimate; for the GPU, the planner's work model on the graph's degree
+statistics), except that a request waiting longer than `age_s` goes first in
+arrival order, so heavy requests are delayed, never starved.
+
 Latency = completion time - submission time (host clock).  `stats()` gives
 p50 / p99 latency and counts/s over the completed requests.
 """
@@ -79,6 +85,15 @@ class GpuBackend:
             raise XminerError(-1, lib().xm_last_error().decode())
         return int(ws) + 24 * len(plans)
 
+    def cost(self, graph_id, pattern, pin_vertex=None) -> float:
+        """The planner's work estimate for this request (cached with the plan)."""
+        p = self.plan(graph_id, pattern, pin_vertex)
+        c = getattr(p, "_est_cost", None)
+        if c is None:
+            c = float(p.describe().get("est_cost", 0.0))
+            p._est_cost = c
+        return c
+
     def new_slot(self):
         return self.torch.cuda.Stream()
 
@@ -103,7 +118,11 @@ class GpuBackend:
 
 class Server:
     def __init__(self, backend, hbm_budget: int, slots: int = 4, max_batch: int = 32,
-                 poll_s: float = 0.0002):
+                 poll_s: float = 0.0002, policy: str = "fifo", age_s: float = 2.0):
+        if policy not in ("fifo", "sjf"):
+            raise ValueError("policy must be 'fifo' or 'sjf'")
+        self.policy = policy
+        self.age_s = age_s
         self.backend = backend
         self.hbm_budget = int(hbm_budget)
         self.max_batch = max_batch
@@ -180,13 +199,24 @@ class Server:
                 self.pending.popleft()
                 self._finish(head, XM_ERR_CANCELLED, None)
                 continue
-            # gather requests on the same graph (and anchor node) in arrival order
+            sjf = self.policy == "sjf"
+            est = lambda r: self.backend.cost(r.graph_id, r.pattern, r.pin[0] if r.pin else None)  # noqa: E731
+            if sjf and now - head.submitted <= self.age_s:
+                # the cheapest pending request leads; the rest keep arrival order
+                head = min(self.pending, key=lambda r: (est(r), r.rid))
+                self.pending.remove(head)
+                self.pending.appendleft(head)
+            # gather requests on the same graph (and anchor node) in arrival
+            # order; under sjf only those within 8x of the head's cost, so a
+            # light launch is not held up by a heavy plan in it
             node = head.pin[1] if head.pin else None
+            head_est = est(head) if sjf else 0.0
             batch, rest = [], collections.deque()
             while self.pending:
                 r = self.pending.popleft()
                 r_node = r.pin[1] if r.pin else None
-                if r.graph_id == head.graph_id and r_node == node and len(batch) < self.max_batch and (
+                similar = not sjf or r is head or (head_est / 8 <= est(r) <= head_est * 8)
+                if r.graph_id == head.graph_id and r_node == node and len(batch) < self.max_batch and similar and (
                         r.deadline is None or now <= r.deadline):
                     batch.append(r)
                 else:

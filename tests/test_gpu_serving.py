@@ -159,3 +159,24 @@ def test_anchored_counts_equal_oracle_and_sum_to_total(xa):
             for reduced in (True, False):
                 got = xa.count_anchored(G, p, v, nodes, reduced=reduced)
                 assert got == want, (name, v, reduced)
+
+
+def test_side_stream_launch_waits_for_setup(xa):
+    """A Counter's buffers are zeroed on torch's current stream; a launch on
+    another stream must still see them zeroed before it writes counts."""
+    import torch
+    banner("launch on a side stream while the current stream is busy")
+    g = xmgen.rmat(9, seed=6)
+    G = xa.Graph(g)
+    pats = [xmgen.named(n) for n in ["ffl", "c4"]]
+    want = [oracle.count(g, p) for p in pats]
+    plans = [xa.Plan(p, graph=G) for p in pats]
+    s = torch.cuda.Stream()
+    for _ in range(3):
+        torch.cuda._sleep(200_000_000)  # a bounded spin on the current stream
+        c = xa.Counter(G, plans)        # its zero fills queue behind the spin
+        c.run(s)
+        s.synchronize()
+        torch.cuda.synchronize()
+        counts, status = c.results()
+        assert status == [0, 0] and counts == want

@@ -12,8 +12,9 @@ from paper_2404_11105_amd.serve import XM_ERR_ADMISSION, XM_ERR_CANCELLED, Serve
 
 
 class FakeBackend:
-    def __init__(self, graphs, secs_per_plan=0.002, ws_bytes=1000):
+    def __init__(self, graphs, secs_per_plan=0.002, ws_bytes=1000, scale_by_cost=False):
         self.graphs = graphs
+        self.scale_by_cost = scale_by_cost
         self.secs = secs_per_plan
         self.ws = ws_bytes
         self.launched = []
@@ -23,6 +24,9 @@ class FakeBackend:
 
     def plan(self, graph_id, pattern, pin_vertex=None):
         return (pattern, pin_vertex)
+
+    def cost(self, graph_id, pattern, pin_vertex=None):
+        return float(len(pattern.arcs))
 
     def footprint(self, graph_id, plans, node=None):
         return self.ws + 24 * len(plans)
@@ -40,7 +44,8 @@ class FakeBackend:
             self.inflight += 1
             self.max_inflight = max(self.max_inflight, self.inflight)
             self.launched.append((graph_id, len(plans)))
-        return {"t": time.perf_counter() + self.secs * len(plans), "counts": counts, "done": False}
+        secs = sum(self.secs * (self.cost(graph_id, p) if self.scale_by_cost else 1.0) for p, _ in plans)
+        return {"t": time.perf_counter() + secs, "counts": counts, "done": False}
 
     def poll(self, h):
         if time.perf_counter() >= h["t"]:
@@ -137,3 +142,34 @@ def test_anchored_requests_batch_by_node_and_sum_to_the_total():
     s.close()
     # anchored requests on the same node share launches
     assert any(n > 1 for _, n in be.launched[1:])
+
+
+def test_sjf_runs_cheap_requests_first_without_starving_heavy_ones():
+    """Policy sjf: with one slot busy, queued cheap requests run before a
+    heavier one that arrived earlier; once a request has waited age_s it
+    goes first; every count is unchanged."""
+    G = {"u": xmgen.uniform_digraph(100, 600, 2)}
+    heavy, light = xmgen.named("c5chord"), xmgen.named("arc")
+    be = FakeBackend(G, secs_per_plan=0.01, scale_by_cost=True)
+    s = Server(be, hbm_budget=10 ** 6, slots=1, max_batch=1, policy="sjf", age_s=30.0)
+    first = s.submit("u", light)          # occupies the slot
+    time.sleep(0.002)
+    fh = s.submit("u", heavy)
+    fl = [s.submit("u", light) for _ in range(3)]
+    for f in [first, fh] + fl:
+        f.result(timeout=60)
+    done = {r.rid: r.done for r in s.completed}
+    s.close()
+    assert all(done[i] < done[1] for i in (2, 3, 4)), "cheap requests should overtake the heavy one"
+    assert fh.result()[0] == oracle.count(G["u"], heavy)
+    # aging: with age_s = 0 the order is arrival order
+    be = FakeBackend(G, secs_per_plan=0.01, scale_by_cost=True)
+    s = Server(be, hbm_budget=10 ** 6, slots=1, max_batch=1, policy="sjf", age_s=0.0)
+    futs = [s.submit("u", light)]
+    time.sleep(0.002)
+    futs += [s.submit("u", heavy)] + [s.submit("u", light) for _ in range(3)]
+    for f in futs:
+        f.result(timeout=60)
+    done = {r.rid: r.done for r in s.completed}
+    s.close()
+    assert all(done[1] < done[i] for i in (2, 3, 4))
