@@ -93,21 +93,29 @@ __device__ __forceinline__ const uint32_t* off_of(const DevGraph& g, uint32_t di
     return dir ? g.in_off : g.out_off;
 }
 
-// Word `w` of the dense rows (the rows take less than 16 GiB, so word
-// offsets fit 32 bits).
-__device__ __forceinline__ uint32_t row_word(const DevGraph& g, uint32_t w) { return g.rows[w]; }
-
-// A probe list (offset o, length l) of node nd becomes a row reference
-// (o = word offset of the row, l = kRowLen) when the list has a row.
-__device__ __forceinline__ void to_row(const DevGraph& g, uint32_t dir, uint32_t nd, uint32_t& o, uint32_t& l) {
-    if (l != kSkip && l >= g.row_min) {
+// The probe of list (dir, node nd) at adjacency offset o with length l: the
+// list itself, or its dense row (length kRowLen) when it has one.
+__device__ __forceinline__ const uint32_t* probe_ref(const DevGraph& g, uint32_t dir, uint32_t nd, uint32_t o,
+                                                     uint32_t& l) {
+    if (l >= g.row_min) {
         const uint2 r = g.row_of[nd];
         const uint32_t row = dir ? r.y : r.x;
         if (row != kSkip) {
-            o = row * g.row_words;
             l = kRowLen;
+            return g.rows + (uint64_t)row * g.row_words;
         }
     }
+    return adj_of(g, dir) + o;
+}
+
+__device__ __forceinline__ const uint32_t* join_ptr(uint32_t lo, uint32_t hi) {
+    return reinterpret_cast<const uint32_t*>(((uint64_t)hi << 32) | lo);
+}
+
+// Any address that may be read (a lane with nothing to probe reads it and
+// ignores the value).
+__device__ __forceinline__ const uint32_t* safe_ptr(const DevGraph& g) {
+    return reinterpret_cast<const uint32_t*>(g.deg);
 }
 
 // Per-level constraint fields, loaded once into scalar registers.
@@ -156,14 +164,15 @@ __device__ void add_u128(unsigned long long* c, unsigned long long lo, unsigned 
 struct Lds {
     uint32_t* bound;     // [kMaxK][64]
     uint32_t* anc;       // [kMaxK][64]
-    uint32_t* base_off;  // [64]
+    uint32_t* base_lo;   // [64]: address of the parent's base list (low word)
     uint32_t* base_len;  // [64]
-    uint32_t* base_kind; // [64]: 0 out list, 1 in list, 2 level buffer
+    uint32_t* base_hi;   // [64]: (high word)
     uint32_t* incl;      // [64]
     uint32_t* segcnt;    // [64]
     uint32_t* mark;      // [128]: tile parent marks
-    uint32_t* chk_off;   // [maxc][64]
-    uint32_t* chk_len;   // [maxc][64]
+    uint32_t* slot_len;  // [maxc][64]: probe k of the parent: list length, kRowLen, or kSkip
+    uint32_t* slot_lo;   // [maxc][64]: address of the list or of the dense row (low word)
+    uint32_t* slot_hi;   // [maxc][64]: (high word)
     uint32_t* hist;      // [64][16]
     uint32_t* st;        // wave state: cur[8], pofs[8], n[8]
     uint32_t* mbuf;      // [kMergeChunk]: probe-list chunk of the cooperative merge
@@ -174,16 +183,17 @@ __device__ __forceinline__ Lds carve(uint32_t* w, uint32_t rows, uint32_t maxc, 
     s.bound = w;
     s.anc = w + rows * 64;
     uint32_t* q = w + 2 * rows * 64;
-    s.base_off = q;
+    s.base_lo = q;
     s.base_len = q + 64;
-    s.base_kind = q + 128;
+    s.base_hi = q + 128;
     s.incl = q + 192;
     s.segcnt = q + 256;
     s.mark = q + 384;
     q += 8 * 64;
-    s.chk_off = q;
-    s.chk_len = q + maxc * 64;
-    q += 2 * maxc * 64;
+    s.slot_len = q;
+    s.slot_lo = q + maxc * 64;
+    s.slot_hi = q + 2 * maxc * 64;
+    q += 3 * maxc * 64;
     s.mbuf = q;
     q += merge ? kMergeChunk : 0;
     s.st = q;
@@ -227,9 +237,9 @@ __device__ __forceinline__ uint32_t level1_len(const DevGraph& g, const PlanDesc
 }
 
 // Phase A of a level: lane = one partial match (parent) of the window.  Walks
-// the parent chain into LDS (bound nodes, ancestor indices) and picks the base
-// list and the lists to probe (long ones as dense rows).  Returns the base
-// length.
+// the parent chain into LDS (bound nodes, ancestor indices), picks the base
+// list and writes the probes (the other constraint lists, long ones as their
+// dense rows) into the parent's probe slots.  Returns the base length.
 template <bool IS_SIG>
 __device__ uint32_t phase_a(Ctx& C, const LK& D, uint32_t lv, uint32_t p, bool pv, bool walk) {
     const KArgs& a = *C.a;
@@ -249,6 +259,14 @@ __device__ uint32_t phase_a(Ctx& C, const LK& D, uint32_t lv, uint32_t p, bool p
             if (l > 0) idx = F.parent[idx];
         }
     }
+    auto put = [&](uint32_t k, const uint32_t* ptr, uint32_t l) {
+        const uint64_t v = reinterpret_cast<uint64_t>(ptr);
+        C.s.slot_len[k * 64 + lane] = l;
+        C.s.slot_lo[k * 64 + lane] = (uint32_t)v;
+        C.s.slot_hi[k * 64 + lane] = (uint32_t)(v >> 32);
+    };
+    const uint32_t* base = nullptr;
+    uint32_t k = 0;
     bool fetched = false;
     if (D.reuse != kNoReuse) {
         uint32_t r = D.reuse;
@@ -256,50 +274,43 @@ __device__ uint32_t phase_a(Ctx& C, const LK& D, uint32_t lv, uint32_t p, bool p
         Lvl F = lvl_arrays(C.scr, a.cap, r - 1);
         uint32_t sc = F.segc[ai];
         if (sc & kComplete) {
-            C.s.base_kind[lane] = 2;
-            C.s.base_off[lane] = F.segb[ai];
+            base = lvl_arrays(C.scr, a.cap, r).node + F.segb[ai];
             len = sc & ~kComplete;
             for (uint32_t c = 0; c < D.n_cons; c++) {
-                uint32_t l = kSkip, o = 0;
-                if ((D.extra >> c) & 1u) {
-                    const uint32_t nd = C.s.bound[D.lvl(c) * 64 + lane];
-                    const uint32_t* off = off_of(g, D.dir(c));
-                    o = off[nd];
-                    l = off[nd + 1] - o;
-                    to_row(g, D.dir(c), nd, o, l);
-                }
-                C.s.chk_off[c * 64 + lane] = o;
-                C.s.chk_len[c * 64 + lane] = l;
+                if (!((D.extra >> c) & 1u)) continue;
+                const uint32_t nd = C.s.bound[D.lvl(c) * 64 + lane];
+                const uint32_t* off = off_of(g, D.dir(c));
+                const uint32_t o = off[nd];
+                uint32_t l = off[nd + 1] - o;
+                const uint32_t* ptr = probe_ref(g, D.dir(c), nd, o, l);
+                put(k++, ptr, l);
             }
             fetched = true;
         }
     }
     if (!fetched) {
+        // the shortest list is the base; the others are probed
         uint32_t best = kSkip, bc = 0, bo = 0;
         for (uint32_t c = 0; c < D.n_cons; c++) {
             const uint32_t nd = C.s.bound[D.lvl(c) * 64 + lane];
             const uint32_t* off = off_of(g, D.dir(c));
-            uint32_t o = off[nd];
-            uint32_t l = off[nd + 1] - o;
-            C.s.chk_off[c * 64 + lane] = o;
-            C.s.chk_len[c * 64 + lane] = l;
+            const uint32_t o = off[nd], l = off[nd + 1] - o;
             if (l < best) {
                 best = l;
                 bc = c;
                 bo = o;
             }
         }
-        C.s.chk_len[bc * 64 + lane] = kSkip;
-        // long probe lists are tested in their dense rows
         for (uint32_t c = 0; c < D.n_cons; c++) {
-            uint32_t o = C.s.chk_off[c * 64 + lane], l = C.s.chk_len[c * 64 + lane];
-            if (c == bc || l < g.row_min) continue;
-            to_row(g, D.dir(c), C.s.bound[D.lvl(c) * 64 + lane], o, l);
-            C.s.chk_off[c * 64 + lane] = o;
-            C.s.chk_len[c * 64 + lane] = l;
+            if (c == bc) continue;
+            const uint32_t nd = C.s.bound[D.lvl(c) * 64 + lane];
+            const uint32_t* off = off_of(g, D.dir(c));
+            const uint32_t o = off[nd];
+            uint32_t l = off[nd + 1] - o;
+            const uint32_t* ptr = probe_ref(g, D.dir(c), nd, o, l);
+            put(k++, ptr, l);
         }
-        C.s.base_kind[lane] = D.dir(bc);
-        C.s.base_off[lane] = bo;
+        base = adj_of(g, D.dir(bc)) + bo;
         len = best;
         if (!IS_SIG && lv == 1) {
             // a root carries its first-level range [lo, hi)
@@ -307,20 +318,28 @@ __device__ uint32_t phase_a(Ctx& C, const LK& D, uint32_t lv, uint32_t p, bool p
             uint32_t lo = F0.parent[p], hi = F0.aux[p];
             hi = hi < len ? hi : len;
             lo = lo < hi ? lo : hi;
-            C.s.base_off[lane] = bo + lo;
+            base += lo;
             len = hi - lo;
         }
     }
+    for (; k < D.n_cons; k++) put(k, safe_ptr(g), kSkip);
+    const uint64_t bv = reinterpret_cast<uint64_t>(base);
+    C.s.base_lo[lane] = (uint32_t)bv;
+    C.s.base_hi[lane] = (uint32_t)(bv >> 32);
     C.s.base_len[lane] = len;
     return len;
 }
 
-// Fetch base element `local` of window parent j.
-__device__ __forceinline__ uint32_t base_elem(const Ctx& C, uint32_t j, uint32_t local, uint32_t reuse) {
-    uint32_t kind = C.s.base_kind[j];
-    uint32_t off = C.s.base_off[j] + local;
-    if (kind == 2) return lvl_arrays(C.scr, C.a->cap, reuse).node[off];
-    return adj_of(C.a->g, kind)[off];
+// Probe slots a level uses: all but the base constraint, or (when reusing a
+// complete candidate set) the extra constraints; lanes with fewer pad with
+// kSkip.
+__device__ __forceinline__ uint32_t n_slots(const LK& D) {
+    return D.reuse == kNoReuse ? (D.n_cons ? D.n_cons - 1 : 0) : D.n_cons;
+}
+
+// Base element `local` of window parent j.
+__device__ __forceinline__ uint32_t base_elem(const Ctx& C, uint32_t j, uint32_t local) {
+    return join_ptr(C.s.base_lo[j], C.s.base_hi[j])[local];
 }
 
 // Window parents of the elements t0 + lane (tile a) and t0 + 64 + lane (tile
@@ -344,34 +363,42 @@ __device__ __forceinline__ void tile_parents(const Lds& s, uint32_t lane, uint32
 }
 
 // Two sorted-list searches per lane (one per element), both loads of a step
-// issued together.  Lanes without a search pass n = 0 (offset 0 is then read
-// and ignored; the caller runs this only when some lane has a non-empty list,
-// so the adjacency array is not empty).
-__device__ __forceinline__ void search2(const uint32_t* __restrict__ adj, uint32_t oa, uint32_t na, uint32_t xa,
-                                        bool& fa, uint32_t ob, uint32_t nb, uint32_t xb, bool& fb) {
-    uint32_t ba = oa, bb = ob, ra = na, rb = nb;
+// issued together.  A lane without a search passes n = 0 and a readable
+// pointer (its value is ignored).
+__device__ __forceinline__ void search2(const uint32_t* __restrict__ A, uint32_t na, uint32_t xa, bool& fa,
+                                        const uint32_t* __restrict__ B, uint32_t nb, uint32_t xb, bool& fb) {
+    uint32_t ba = 0, bb = 0, ra = na, rb = nb;
     while (__ballot(ra > 1 || rb > 1)) {
         const uint32_t ha = ra >> 1, hb = rb >> 1;
-        const uint32_t va = adj[ba + ha], vb = adj[bb + hb];
+        const uint32_t va = A[ba + ha], vb = B[bb + hb];
         ba = (va <= xa) ? ba + ha : ba;
         bb = (vb <= xb) ? bb + hb : bb;
         ra -= ha;
         rb -= hb;
     }
-    const uint32_t ea = adj[ba], eb = adj[bb];
+    const uint32_t ea = A[ba], eb = B[bb];
     fa = na > 0 && ea == xa;
     fb = nb > 0 && eb == xb;
 }
 
+// Membership of x in probe (ptr, len) for one lane: a dense-row bit or a
+// sorted-list search (no test when len is kSkip: returns true).
+__device__ __forceinline__ bool probe_one(const uint32_t* ptr, uint32_t len, uint32_t x) {
+    if (len == kSkip) return true;
+    if (len == kRowLen) return (ptr[x >> 5] >> (x & 31u)) & 1u;
+    return contains(ptr, len, x);
+}
+
 // Candidate tests of two elements (xa of window parent ja, xb of jb) against
-// level D: injectivity, degree thresholds, then each probe list as a dense-row
-// bit test or a sorted-list search.  oka / okb: in = element valid, out =
-// element passes.
-__device__ __forceinline__ void check_pair(const Ctx& C, const LK& D, uint32_t lv, uint32_t ja, uint32_t xa,
-                                           bool& oka, uint32_t jb, uint32_t xb, bool& okb) {
+// level D: injectivity (levels in `inj`), degree thresholds, then each probe
+// slot as a dense-row bit test or a sorted-list search.  oka / okb: in =
+// element valid, out = element passes.
+__device__ __forceinline__ void check_pair(const Ctx& C, const LK& D, uint32_t inj, uint32_t lv, uint32_t ns,
+                                           uint32_t ja, uint32_t xa, bool& oka, uint32_t jb, uint32_t xb,
+                                           bool& okb) {
     const DevGraph& g = C.a->g;
     for (uint32_t l = 0; l < lv; l++)
-        if ((D.inj >> l) & 1u) {
+        if ((inj >> l) & 1u) {
             oka = oka && (xa != C.s.bound[l * 64 + ja]);
             okb = okb && (xb != C.s.bound[l * 64 + jb]);
         }
@@ -380,13 +407,15 @@ __device__ __forceinline__ void check_pair(const Ctx& C, const LK& D, uint32_t l
         oka = oka && da.x >= D.dmin_out && da.y >= D.dmin_in;
         okb = okb && db.x >= D.dmin_out && db.y >= D.dmin_in;
     }
-    for (uint32_t c = 0; c < D.n_cons; c++) {
-        const uint32_t lA = C.s.chk_len[c * 64 + ja], lB = C.s.chk_len[c * 64 + jb];
-        const uint32_t oA = C.s.chk_off[c * 64 + ja], oB = C.s.chk_off[c * 64 + jb];
+    const uint32_t* safe = safe_ptr(g);
+    for (uint32_t k = 0; k < ns; k++) {
+        const uint32_t lA = C.s.slot_len[k * 64 + ja], lB = C.s.slot_len[k * 64 + jb];
+        const uint32_t* pA = join_ptr(C.s.slot_lo[k * 64 + ja], C.s.slot_hi[k * 64 + ja]);
+        const uint32_t* pB = join_ptr(C.s.slot_lo[k * 64 + jb], C.s.slot_hi[k * 64 + jb]);
         const bool rA = oka && lA == kRowLen, rB = okb && lB == kRowLen;
         if (__ballot(rA || rB)) {
-            const uint32_t wa = row_word(g, rA ? oA + (xa >> 5) : 0u);
-            const uint32_t wb = row_word(g, rB ? oB + (xb >> 5) : 0u);
+            const uint32_t wa = (rA ? pA : safe)[rA ? (xa >> 5) : 0u];
+            const uint32_t wb = (rB ? pB : safe)[rB ? (xb >> 5) : 0u];
             if (rA) oka = (wa >> (xa & 31u)) & 1u;
             if (rB) okb = (wb >> (xb & 31u)) & 1u;
         }
@@ -396,11 +425,25 @@ __device__ __forceinline__ void check_pair(const Ctx& C, const LK& D, uint32_t l
         const bool sa = oka && lA < kRowLen, sb = okb && lB < kRowLen;
         if (__ballot(sa || sb)) {
             bool fa, fb;
-            search2(adj_of(g, D.dir(c)), sa ? oA : 0u, sa ? lA : 0u, xa, fa, sb ? oB : 0u, sb ? lB : 0u, xb, fb);
+            search2(sa ? pA : safe, sa ? lA : 0u, xa, fa, sb ? pB : safe, sb ? lB : 0u, xb, fb);
             if (sa) oka = fa;
             if (sb) okb = fb;
         }
     }
+}
+
+// Whether bound node y of this lane's partial match lies in the lane's base
+// list and passes all its probes: then a flattened pass without injectivity
+// counted it once.
+__device__ __forceinline__ bool bound_in_set(const Ctx& C, uint32_t ns, uint32_t y) {
+    const uint32_t lane = C.lane;
+    const uint32_t len = C.s.base_len[lane];
+    if (!contains(join_ptr(C.s.base_lo[lane], C.s.base_hi[lane]), len, y)) return false;
+    for (uint32_t k = 0; k < ns; k++)
+        if (!probe_one(join_ptr(C.s.slot_lo[k * 64 + lane], C.s.slot_hi[k * 64 + lane]),
+                       C.s.slot_len[k * 64 + lane], y))
+            return false;
+    return true;
 }
 
 // Expand one window of level lv from the parents in level lv-1.  Returns the
@@ -441,7 +484,7 @@ __device__ uint32_t expand(Ctx& C, uint32_t lv) {
     wave_sync();
     Lvl Fo = lvl_arrays(C.scr, cap, lv);
     uint32_t nout = 0, carry = 0;
-    const uint32_t reuse = D.reuse;
+    const uint32_t ns = n_slots(D);
     // two tiles per step: survivors of tile a are written before those of
     // tile b, so each parent's children stay contiguous and in order
     for (uint32_t t0 = 0; t0 < T; t0 += 128) {
@@ -454,9 +497,9 @@ __device__ uint32_t expand(Ctx& C, uint32_t lv) {
         const uint32_t lb = gb - (jb ? C.s.incl[jb - 1] : 0u) + (jb == 0 ? pofs : 0u);
         oka = oka && la < C.s.base_len[ja];
         okb = okb && lb < C.s.base_len[jb];
-        if (oka) xa = base_elem(C, ja, la, reuse);
-        if (okb) xb = base_elem(C, jb, lb, reuse);
-        check_pair(C, D, lv, ja, xa, oka, jb, xb, okb);
+        if (oka) xa = base_elem(C, ja, la);
+        if (okb) xb = base_elem(C, jb, lb);
+        check_pair(C, D, D.inj, lv, ns, ja, xa, oka, jb, xb, okb);
         const uint64_t ma = __ballot(oka);
         if (oka) {
             const uint32_t pos = nout + rank_below(ma);
@@ -596,6 +639,7 @@ __device__ void leaf_masks(Ctx& C, uint32_t nb, uint32_t p, bool pv) {
             }
         } else {
             const uint32_t len = phase_a<true>(C, K, nb, p, pv, false);
+            const uint32_t ns = n_slots(K);
             const uint32_t incl = scan_incl(len, lane);
             C.s.incl[lane] = incl;
             const uint32_t T = uni(__shfl(incl, 63, 64));
@@ -612,12 +656,17 @@ __device__ void leaf_masks(Ctx& C, uint32_t nb, uint32_t p, bool pv) {
                 bool oka = ga < T && la < C.s.base_len[ja];
                 bool okb = gb < T && lb < C.s.base_len[jb];
                 uint32_t xa = 0, xb = 0;
-                if (oka) xa = base_elem(C, ja, la, K.reuse);
-                if (okb) xb = base_elem(C, jb, lb, K.reuse);
-                check_pair(C, K, nb, ja, xa, oka, jb, xb, okb);
+                if (oka) xa = base_elem(C, ja, la);
+                if (okb) xb = base_elem(C, jb, lb);
+                // injectivity is settled per partial match below
+                check_pair(C, K, 0u, nb, ns, ja, xa, oka, jb, xb, okb);
                 const uint64_t ba = __ballot(oka), bb = __ballot(okb);
                 if (owns) h += own_count(ba, start, len, t0) + own_count(bb, start, len, t0 + 64);
             }
+            // the bound nodes the set may not contain were counted if present
+            if (pv)
+                for (uint32_t b = 0; b < nb; b++)
+                    if (((K.inj >> b) & 1u) && bound_in_set(C, ns, C.s.bound[b * 64 + lane])) h -= 1;
             wave_sync();
         }
         C.s.hist[lane * 16 + M] = h;
@@ -699,15 +748,16 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
             // pairs leave the flattened pass for the cooperative merge
             uint32_t probe_c = kSkip;
             bool big = false;
+            const uint32_t ns = n_slots(S);
             if (linear && pv) {
                 uint32_t nprobe = 0;
-                for (uint32_t c = 0; c < S.n_cons; c++)
-                    if (C.s.chk_len[c * 64 + lane] != kSkip) {
+                for (uint32_t c = 0; c < ns; c++)
+                    if (C.s.slot_len[c * 64 + lane] != kSkip) {
                         probe_c = c;
                         nprobe++;
                     }
-                if (nprobe == 1 && C.s.chk_len[probe_c * 64 + lane] != kRowLen) {
-                    uint32_t pl = C.s.chk_len[probe_c * 64 + lane];
+                if (nprobe == 1 && C.s.slot_len[probe_c * 64 + lane] != kRowLen) {
+                    uint32_t pl = C.s.slot_len[probe_c * 64 + lane];
                     uint32_t mn = len < pl ? len : pl, mx = len < pl ? pl : len;
                     big = mn >= a.merge_min && (uint64_t)mx <= (uint64_t)a.merge_ratio * mn;
                 }
@@ -732,29 +782,32 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
                 bool oka = ga < T && la < C.s.base_len[ja];
                 bool okb = gb < T && lb < C.s.base_len[jb];
                 uint32_t xa = 0, xb = 0;
-                if (oka) xa = base_elem(C, ja, la, S.reuse);
-                if (okb) xb = base_elem(C, jb, lb, S.reuse);
-                check_pair(C, S, nb, ja, xa, oka, jb, xb, okb);
+                if (oka) xa = base_elem(C, ja, la);
+                if (okb) xb = base_elem(C, jb, lb);
+                // injectivity is settled per partial match below
+                check_pair(C, S, 0u, nb, ns, ja, xa, oka, jb, xb, okb);
                 // one leaf: survivors are only counted
                 lin += (unsigned long long)(__popcll(__ballot(oka)) + __popcll(__ballot(okb)));
+            }
+            // bound nodes the leaf may not take were counted if they are in the set
+            for (uint32_t b = 0; b < nb; b++) {
+                if (!((S.inj >> b) & 1u)) continue;
+                const bool hit = pv && !big && bound_in_set(C, ns, C.s.bound[b * 64 + lane]);
+                lin -= (unsigned long long)__popcll(__ballot(hit));
             }
             wave_sync();
             // balanced big pairs, one partial match at a time
             while (bigmask) {
                 const uint32_t j = (uint32_t)__builtin_ctzll(bigmask);
                 bigmask &= bigmask - 1;
-                const uint32_t kind = uni(C.s.base_kind[j]);
-                const uint32_t boff = uni(C.s.base_off[j]);
                 const uint32_t blen = uni(C.s.base_len[j]);
                 uint32_t pc = 0;
-                for (uint32_t c = 0; c < S.n_cons; c++)
-                    if (C.s.chk_len[c * 64 + j] != kSkip) pc = c;
+                for (uint32_t c = 0; c < ns; c++)
+                    if (C.s.slot_len[c * 64 + j] != kSkip) pc = c;
                 pc = uni(pc);
-                const uint32_t poff = uni(C.s.chk_off[pc * 64 + j]);
-                const uint32_t plen = uni(C.s.chk_len[pc * 64 + j]);
-                const uint32_t* A = (kind == 2) ? lvl_arrays(C.scr, a.cap, S.reuse).node + boff
-                                                : adj_of(a.g, kind) + boff;
-                const uint32_t* B = adj_of(a.g, S.dir(pc)) + poff;
+                const uint32_t plen = uni(C.s.slot_len[pc * 64 + j]);
+                const uint32_t* A = join_ptr(uni(C.s.base_lo[j]), uni(C.s.base_hi[j]));
+                const uint32_t* B = join_ptr(uni(C.s.slot_lo[pc * 64 + j]), uni(C.s.slot_hi[pc * 64 + j]));
                 lin += merge_count(C.s, A, blen, B, plen, S.inj, nb, j, lane);
             }
         }
@@ -846,8 +899,10 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
     const uint64_t gw = (uint64_t)blockIdx.x * kWavesPerBlock + wid;
     C.scr = a.scratch + gw * (uint64_t)a.wave_words;
     C.acc_lo = C.acc_hi = 0;
-    const uint32_t split_count = uni(__atomic_load_n(&a.ctl[kCtlSplitCount], __ATOMIC_RELAXED));
-    const uint32_t n_split = split_count < a.split_cap ? split_count : a.split_cap;
+    // this wave's home split queue: the XCD its block runs on (blocks go to
+    // the 8 XCDs round-robin), so a hub's sub-range tasks share one L2
+    const uint32_t home = blockIdx.x % kQueues;
+    bool split_left = true;
     const uint32_t chunks_per_plan = (a.n_src + a.chunk - 1) / a.chunk;
     const uint32_t total_chunks = chunks_per_plan * a.n_plans;
     Lvl F0 = lvl_arrays(C.scr, a.cap, 0);
@@ -862,11 +917,23 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
                 atomicOr(&a.ctl[kCtlCancelled], 1u);
                 stop = true;
             }
-            if (!stop && __atomic_load_n(&a.ctl[kCtlSplitHead], __ATOMIC_RELAXED) < n_split) {
-                uint32_t it = atomicAdd(&a.ctl[kCtlSplitHead], 1u);
-                if (it < n_split) {
-                    kind = 0;
-                    item = it;
+            // split queues: the home queue first, then the others (stealing);
+            // the split kernel has finished, so an empty queue stays empty
+            if (!stop && split_left) {
+                split_left = false;
+                for (uint32_t t = 0; t < kQueues; t++) {
+                    const uint32_t q = (home + t) % kQueues;
+                    const uint32_t qcap = a.qbase[q + 1] - a.qbase[q];
+                    uint32_t cnt = __atomic_load_n(&a.ctl[kCtlSplitCount0 + q], __ATOMIC_RELAXED);
+                    cnt = cnt < qcap ? cnt : qcap;
+                    if (__atomic_load_n(&a.ctl[kCtlSplitHead0 + q], __ATOMIC_RELAXED) >= cnt) continue;
+                    const uint32_t it = atomicAdd(&a.ctl[kCtlSplitHead0 + q], 1u);
+                    if (it < cnt) {
+                        kind = 0;
+                        item = a.qbase[q] + it;
+                        split_left = true;
+                        break;
+                    }
                 }
             }
             if (!stop && kind == 2) {
@@ -950,15 +1017,18 @@ __global__ void split_kernel(KArgs a) {
         const uint32_t sz = item_size(len, a.split, a.split_work);
         if (len <= sz) continue;
         uint32_t nit = (len + sz - 1) / sz;
-        uint32_t base = atomicAdd(&a.ctl[kCtlSplitCount], nit);
-        if (base + nit > a.split_cap) {
+        // all tasks of one root go to one queue (one XCD's L2)
+        const uint32_t qu = h % kQueues;
+        const uint32_t qcap = a.qbase[qu + 1] - a.qbase[qu];
+        uint32_t base = atomicAdd(&a.ctl[kCtlSplitCount0 + qu], nit);
+        if (base + nit > qcap) {
             atomicOr(&a.ctl[kCtlQueueFull], 1u);
             continue;
         }
         for (uint32_t q = 0; q < nit; q++) {
             uint32_t lo = q * sz;
             uint32_t hi = lo + sz < len ? lo + sz : len;
-            a.split_items[base + q] = make_uint4(pi, r, lo, hi);
+            a.split_items[a.qbase[qu] + base + q] = make_uint4(pi, r, lo, hi);
         }
     }
 }

@@ -17,13 +17,15 @@ constexpr uint32_t kMergeMin = 0xFFFFFFFFu;  // default: merge off (see xm_count
 constexpr uint32_t kMergeRatio = 16;  // ... and within this length ratio -> merge
 
 // Control words at the start of the workspace.
+constexpr uint32_t kQueues = 8;  // split-task queues, one per XCD (8 XCDs on MI355X)
+
 enum Ctl : uint32_t {
     kCtlRootCursor = 0,   // next root chunk
-    kCtlSplitHead = 1,    // next split item
-    kCtlSplitCount = 2,   // split items written by the split kernel
     kCtlCancelled = 3,    // a wave saw the cancel flag
     kCtlQueueFull = 4,    // split queue overflow (cannot happen with a sized workspace)
     kCtlBadPlan = 5,      // a level had more constraints than the layout holds (cannot happen)
+    kCtlSplitHead0 = 8,   // [kQueues]: next item of split queue q
+    kCtlSplitCount0 = 16, // [kQueues]: items the split kernel wrote to queue q
     kCtlWords = 64
 };
 
@@ -64,8 +66,9 @@ struct KArgs {
     uint32_t cap;               // entries per level buffer
     uint32_t* ctl;              // control words
     uint32_t* plan_flags;       // per plan: bit 0 overflow
-    uint4* split_items;         // (plan, root, lo, hi)
+    uint4* split_items;         // (plan, root, lo, hi); queue q holds [qbase[q], qbase[q+1])
     uint32_t split_cap;
+    uint32_t qbase[kQueues + 1];
     uint32_t n_src;             // roots: subset size or n
     const uint32_t* roots;      // subset or NULL (then root i is node i)
     const uint32_t* hubs;       // hub candidates for the split kernel (when roots == NULL)
@@ -113,7 +116,7 @@ inline uint32_t lds_words_for(uint32_t rows, uint32_t maxc, bool nonlinear, bool
     return 2 * rows * 64       // bound values, ancestor indices
            + 8 * 64            // base offset/length/kind, inclusive scan, segment counts, spare,
                                // tile parent marks (2 x 64)
-           + 2 * maxc * 64     // check-list offset/length per constraint
+           + 3 * maxc * 64     // probe slots: length, address (two words) per constraint
            + (merge ? kMergeChunk : 0)  // merge chunk
            + (nonlinear ? 16 * 64 : 0)  // leaf-group histograms
            + 32;               // wave state

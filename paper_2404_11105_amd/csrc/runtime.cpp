@@ -98,6 +98,7 @@ struct Layout {
     bool nonlinear;
     size_t off_ctl, off_flags, off_table, off_split, off_scratch, total;
     uint32_t split_cap, wave_words, lds_words;
+    uint32_t qbase[xm::kQueues + 1];
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -175,8 +176,12 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
         uint32_t sz = xm::item_size(len, L.split, sw);
         return len > sz ? (len + sz - 1) / sz : 0;
     };
+    // per queue: a root's tasks go to queue (its index in the hub list or
+    // the subset) mod kQueues
+    uint64_t qc[xm::kQueues];
     auto count_items = [&](uint32_t sw) -> uint64_t {
         uint64_t tot = 0;
+        for (uint32_t q = 0; q < xm::kQueues; q++) qc[q] = 0;
         if (o && o->roots_dev && roots_host) {
             // exact, from the subset's degrees
             for (uint32_t i = 0; i < n_plans; i++) {
@@ -190,13 +195,18 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
                     if (d.x < D.root_dout || d.y < D.root_din) continue;
                     uint32_t L1 = 0xFFFFFFFFu;
                     for (int c = 0; c < D.lvl[1].n_cons; c++) L1 = std::min(L1, D.lvl[1].cons_dir[c] ? d.y : d.x);
-                    tot += pieces(L1, sw);
+                    const uint64_t pc = pieces(L1, sw);
+                    tot += pc;
+                    qc[k % xm::kQueues] += pc;
                 }
             }
             return tot;
         }
         if (o && o->roots_dev) {  // subset degrees are not known on the host: bound them
-            return (uint64_t)o->n_roots * pieces(max_list, sw) * splittable;
+            const uint64_t per = pieces(max_list, sw) * splittable;
+            for (uint32_t q = 0; q < xm::kQueues; q++)
+                qc[q] = (o->n_roots > q ? ((uint64_t)o->n_roots - q + xm::kQueues - 1) / xm::kQueues : 0) * per;
+            return (uint64_t)o->n_roots * per;
         }
         for (uint32_t i = 0; i < n_plans; i++) {
             const PlanDesc& D = plans[i]->desc;
@@ -206,7 +216,9 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
                 if (d.x < D.root_dout || d.y < D.root_din) continue;
                 uint32_t L1 = 0xFFFFFFFFu;
                 for (int c = 0; c < D.lvl[1].n_cons; c++) L1 = std::min(L1, D.lvl[1].cons_dir[c] ? d.y : d.x);
-                tot += pieces(L1, sw);
+                const uint64_t pc = pieces(L1, sw);
+                tot += pc;
+                qc[h % xm::kQueues] += pc;
             }
         }
         return tot;
@@ -218,6 +230,8 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
     }
     if (items > 0xFFFFFFF0ull) return fail(XM_ERR_INVALID, "split queue too large; raise split_work");
     L.split_cap = (uint32_t)std::max<uint64_t>(items, 1);
+    L.qbase[0] = 0;
+    for (uint32_t q = 0; q < xm::kQueues; q++) L.qbase[q + 1] = L.qbase[q] + (uint32_t)qc[q];
     L.wave_words = L.e_max * xm::kLvlArrays * L.cap;
     size_t off = 0;
     L.off_ctl = off;
@@ -270,6 +284,7 @@ int enqueue_count(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const*
     a.plan_flags = reinterpret_cast<uint32_t*>(base + L.off_flags);
     a.split_items = reinterpret_cast<uint4*>(base + L.off_split);
     a.split_cap = L.split_cap;
+    for (uint32_t q = 0; q <= xm::kQueues; q++) a.qbase[q] = L.qbase[q];
     a.roots = (o && o->roots_dev) ? o->roots_dev : nullptr;
     a.n_src = a.roots ? o->n_roots : g->n;
     a.hubs = g->hubs;
