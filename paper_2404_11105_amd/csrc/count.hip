@@ -188,8 +188,8 @@ __device__ __forceinline__ Lds carve(uint32_t* w, uint32_t rows, uint32_t maxc, 
     s.base_hi = q + 128;
     s.incl = q + 192;
     s.segcnt = q + 256;
-    s.mark = q + 384;
-    q += 8 * 64;
+    s.mark = q + 320;
+    q += 7 * 64;
     s.slot_len = q;
     s.slot_lo = q + maxc * 64;
     s.slot_hi = q + 2 * maxc * 64;

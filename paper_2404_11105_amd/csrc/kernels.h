@@ -114,8 +114,8 @@ __host__ __device__ inline uint32_t item_size(uint32_t L1, uint32_t split, uint3
 // the batch), the largest constraint count, and the optional parts.
 inline uint32_t lds_words_for(uint32_t rows, uint32_t maxc, bool nonlinear, bool merge) {
     return 2 * rows * 64       // bound values, ancestor indices
-           + 8 * 64            // base offset/length/kind, inclusive scan, segment counts, spare,
-                               // tile parent marks (2 x 64)
+           + 7 * 64            // base address (2 words) and length, inclusive scan, segment
+                               // counts, tile parent marks (2 x 64)
            + 3 * maxc * 64     // probe slots: length, address (two words) per constraint
            + (merge ? kMergeChunk : 0)  // merge chunk
            + (nonlinear ? 16 * 64 : 0)  // leaf-group histograms
