@@ -171,7 +171,11 @@ int xm_plan_work(uint32_t n, const uint32_t* out_off, const uint32_t* out_adj,
  * Counting (Algorithm 2; sections 5.2-5.3).
  *
  * Counts every plan in plans[0..n_plans) against g in ONE persistent kernel
- * launch (batched form) on hip_stream.  n_plans = 1 is the plain form.
+ * launch (batched form) on hip_stream.  n_plans = 1 is the plain form;
+ * n_plans is at most 65535.  While some waves have run out of queued work,
+ * waves in the middle of a task hand unstarted partial matches (with their
+ * bound prefix) to them through a device queue (work donation), so one heavy
+ * root does not leave the rest of the device idle.
  *
  * counts_dev: caller device buffer of 2*n_plans uint64: (lo, hi) of the
  *             unsigned 128-bit count of plan i at [2i], [2i+1].

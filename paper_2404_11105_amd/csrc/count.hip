@@ -34,6 +34,9 @@ namespace xm {
 static_assert(sizeof(PlanDesc) % 4 == 0, "plan descriptors are copied in 32-bit words");
 
 constexpr uint32_t kSkip = 0xFFFFFFFFu;
+constexpr uint32_t kIdlePolls = 1u << 13;  // polls a waiting wave makes for donated work (at most ~28 us apart)
+constexpr uint32_t kMaxWaiters = 512;      // waves that wait for donated work; the others leave
+constexpr uint32_t kDonateAfter = 256;     // windows a task runs before it may donate
 constexpr uint32_t kComplete = 0x80000000u;
 
 __device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -836,9 +839,65 @@ __device__ void flush(Ctx& C) {
     C.acc_lo = C.acc_hi = 0;
 }
 
-// Depth-first exploration of the roots held in level 0.
+// Work donation.  While some waves are idle (all queues drained), a wave that
+// has spent at least kDonateAfter windows in one task (a straggler: most tasks
+// take a few windows, and a donated subtree is explored less efficiently than
+// in a full window) hands off unstarted partial matches: at the shallowest
+// level l >= 2 with at least two parents at level l-1 not yet expanded, the
+// last half of them (at most 64) become donated tasks, each carrying its
+// prefix phi(v_0..v_{l-1}); the donor drops them from its window.  A donated
+// task is explored from level l by another wave.  Slots are reserved with a
+// CAS on the tail (never past the capacity) and published with a ready flag.
+__device__ void maybe_donate(Ctx& C, uint32_t start, uint32_t lv) {
+    const KArgs& a = *C.a;
+    uint32_t* st = C.s.st;
+    uint32_t idle = 0;
+    if (C.lane == 0) idle = __atomic_load_n(&a.ctl[kCtlIdle], __ATOMIC_RELAXED);
+    if (uni(__shfl(idle, 0, 64)) == 0) return;
+    for (uint32_t l = (start > 2 ? start : 2); l <= lv; l++) {
+        const uint32_t n = uni(st[16 + l - 1]);
+        uint32_t first = uni(st[l]);
+        if (l == lv && uni(st[8 + l]) > 0) first += 1;  // a parent in the middle of a slice stays
+        if (first >= n || n - first < 2) continue;
+        uint32_t k = (n - first) / 2;
+        k = k < 64 ? k : 64;
+        // reserve k slots
+        uint32_t base = kSkip;
+        if (C.lane == 0) {
+            uint32_t t = __atomic_load_n(&a.ctl[kCtlDonTail], __ATOMIC_RELAXED);
+            while (t + k <= a.don_cap) {
+                const uint32_t seen = atomicCAS(&a.ctl[kCtlDonTail], t, t + k);
+                if (seen == t) {
+                    base = t;
+                    break;
+                }
+                t = seen;
+            }
+        }
+        base = uni(__shfl(base, 0, 64));
+        if (base == kSkip) return;  // no room: keep the work
+        if (C.lane < k) {
+            uint32_t* ent = a.don + (uint64_t)(base + C.lane) * kDonWords;
+            uint32_t idx = n - k + C.lane;
+            for (int j = (int)l - 1; j >= 0; --j) {
+                Lvl F = lvl_arrays(C.scr, a.cap, (uint32_t)j);
+                ent[2 + j] = F.node[idx];
+                if (j > 0) idx = F.parent[idx];
+            }
+            ent[0] = C.pi | (l << 16);
+            __threadfence();
+            __atomic_store_n(&ent[1], 1u, __ATOMIC_RELEASE);
+        }
+        if (C.lane == 0) st[16 + l - 1] = n - k;
+        wave_sync();
+        return;
+    }
+}
+
+// Depth-first exploration of the n0 partial matches held in level start-1
+// (start = 1: roots in level 0).
 template <bool NONLIN>
-__device__ void explore(Ctx& C, uint32_t n0) {
+__device__ void explore(Ctx& C, uint32_t n0, uint32_t start) {
     const uint32_t e = C.P->e;
     uint32_t* st = C.s.st;
     if (e == 1) {
@@ -846,23 +905,24 @@ __device__ void explore(Ctx& C, uint32_t n0) {
         return;
     }
     if (C.lane == 0) {
-        st[16 + 0] = n0;
-        st[1] = 0;
-        st[8 + 1] = 0;
+        st[16 + start - 1] = n0;
+        st[start] = 0;
+        st[8 + start] = 0;
     }
     wave_sync();
-    uint32_t lv = 1;
+    uint32_t lv = start;
     uint32_t windows = 0;
     for (;;) {
         uint32_t nparents = uni(st[16 + lv - 1]);
         uint32_t cur = uni(st[lv]);
         if (cur >= nparents) {
-            if (lv == 1) break;
+            if (lv == start) break;
             lv -= 1;
             continue;
         }
+        ++windows;
         // a long task still notices the cancel flag (counts are then partial)
-        if (C.a->cancel && (++windows & 15u) == 0) {
+        if (C.a->cancel && (windows & 15u) == 0) {
             uint32_t stop = 0;
             if (C.lane == 0) stop = __atomic_load_n(C.a->cancel, __ATOMIC_RELAXED) != 0;
             if (uni(__shfl(stop, 0, 64))) {
@@ -870,6 +930,7 @@ __device__ void explore(Ctx& C, uint32_t n0) {
                 break;
             }
         }
+        if (windows >= kDonateAfter && (windows & 7u) == 0 && lv >= 2) maybe_donate(C, start, lv);
         uint32_t nout = expand(C, lv);
         if (lv == e - 1) {
             if (nout) count_leaves<NONLIN>(C, lv, nout);
@@ -910,8 +971,8 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
     for (;;) {
         // ---- take a task
         uint32_t kind = 2, item = 0;
+        bool stop = false;
         if (C.lane == 0) {
-            bool stop = false;
             // the flag may sit in host memory: poll it on every 32nd task only
             if (a.cancel && (taken++ & 31u) == 0 && __atomic_load_n(a.cancel, __ATOMIC_RELAXED) != 0) {
                 atomicOr(&a.ctl[kCtlCancelled], 1u);
@@ -944,10 +1005,37 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
                 }
             }
         }
+        if (C.lane == 0 && kind == 2 && !stop) {
+            // queues drained: wait for donated work while any wave still holds a
+            // task.  At most kMaxWaiters waves wait (the others leave at once),
+            // and they poll with growing pauses, so waiting waves do not crowd
+            // the cache lines the working waves update.
+            if (atomicAdd(&a.ctl[kCtlIdle], 1u) < kMaxWaiters) {
+                uint32_t nap = 1;
+                for (uint32_t polls = 0; polls < kIdlePolls; polls++) {
+                    const uint32_t h = __atomic_load_n(&a.ctl[kCtlDonHead], __ATOMIC_RELAXED);
+                    const uint32_t t = __atomic_load_n(&a.ctl[kCtlDonTail], __ATOMIC_RELAXED);
+                    if (h < t) {
+                        if (atomicCAS(&a.ctl[kCtlDonHead], h, h + 1) == h) {
+                            kind = 3;
+                            item = h;
+                            break;
+                        }
+                        continue;
+                    }
+                    if ((polls & 7u) == 7u && __atomic_load_n(&a.ctl[kCtlActive], __ATOMIC_RELAXED) == 0) break;
+                    if (a.cancel && (polls & 63u) == 0 && __atomic_load_n(a.cancel, __ATOMIC_RELAXED) != 0) break;
+                    for (uint32_t z = 0; z < nap; z++) __builtin_amdgcn_s_sleep(64);  // ~4K cycles each
+                    nap = nap < 16 ? nap * 2 : 16;
+                }
+            }
+            atomicSub(&a.ctl[kCtlIdle], 1u);
+        }
+        if (C.lane == 0 && kind != 2) atomicAdd(&a.ctl[kCtlActive], 1u);
         kind = uni(__shfl(kind, 0, 64));
         item = uni(__shfl(item, 0, 64));
         if (kind == 2) break;
-        uint32_t n0 = 0;
+        uint32_t n0 = 0, start = 1;
         if (kind == 0) {
             uint4 it = a.split_items[item];
             C.pi = uni(it.x);
@@ -958,6 +1046,32 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
                 F0.aux[0] = it.w;
             }
             n0 = 1;
+        } else if (kind == 3) {
+            // a donated prefix: bind levels 0..d-1 as single entries and explore from level d
+            uint32_t* ent = a.don + (uint64_t)item * kDonWords;
+            uint32_t ready = 0;
+            if (C.lane == 0) {
+                for (uint32_t spin = 0; spin < kIdlePolls; spin++) {
+                    ready = __atomic_load_n(&ent[1], __ATOMIC_ACQUIRE);
+                    if (ready) break;
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                if (!ready) atomicOr(&a.ctl[kCtlBadPlan], 1u);  // a reserved slot never published
+            }
+            ready = uni(__shfl(ready, 0, 64));
+            __atomic_thread_fence(__ATOMIC_ACQUIRE);  // every lane reads the entry after its ready flag
+            const uint32_t head = ready ? uni(__atomic_load_n(&ent[0], __ATOMIC_RELAXED)) : (1u << 16);
+            C.pi = head & 0xFFFFu;
+            C.P = a.plans + C.pi;
+            start = head >> 16;
+            if (ready && C.lane < start) {
+                Lvl F = lvl_arrays(C.scr, a.cap, C.lane);
+                F.node[0] = __atomic_load_n(&ent[2 + C.lane], __ATOMIC_RELAXED);
+                F.parent[0] = 0;
+                F.segc[0] = 0;  // no complete child segments: reusers fetch their lists
+                F.aux[0] = kSkip;
+            }
+            n0 = ready ? 1u : 0u;
         } else {
             // interleave plans so that all of them start on the low (hub) ids
             C.pi = uni(item % a.n_plans);
@@ -993,8 +1107,9 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
             n0 = (uint32_t)__popcll(m);
         }
         wave_sync();
-        if (n0) explore<NONLIN>(C, n0);
+        if (n0) explore<NONLIN>(C, n0, start);
         flush(C);
+        if (C.lane == 0) atomicSub(&a.ctl[kCtlActive], 1u);
     }
 }
 
@@ -1047,6 +1162,9 @@ __global__ void init_kernel(InitArgs a) {
         for (uint32_t i = tid; i < kCtlWords; i += nthr) a.ctl[i] = 0;
         for (uint32_t i = tid; i < a.n_plans; i += nthr) a.plan_flags[i] = 0;
         for (uint32_t i = tid; i < 2 * a.n_plans; i += nthr) a.counts[i] = 0;
+        // the workspace is reused across launches (and by the caller's
+        // allocator): a slot is ready only once this launch publishes it
+        for (uint32_t i = tid; i < a.don_cap; i += nthr) a.don[(uint64_t)i * kDonWords + 1] = 0;
     }
 }
 

@@ -18,6 +18,8 @@ constexpr uint32_t kMergeRatio = 16;  // ... and within this length ratio -> mer
 
 // Control words at the start of the workspace.
 constexpr uint32_t kQueues = 8;  // split-task queues, one per XCD (8 XCDs on MI355X)
+constexpr uint32_t kDonWords = 8;  // donated task: plan | depth << 16, ready flag, prefix nodes [6]
+constexpr uint32_t kDonCap = 1u << 18;  // donated-task slots per launch
 
 enum Ctl : uint32_t {
     kCtlRootCursor = 0,   // next root chunk
@@ -26,7 +28,12 @@ enum Ctl : uint32_t {
     kCtlBadPlan = 5,      // a level had more constraints than the layout holds (cannot happen)
     kCtlSplitHead0 = 8,   // [kQueues]: next item of split queue q
     kCtlSplitCount0 = 16, // [kQueues]: items the split kernel wrote to queue q
-    kCtlWords = 64
+    // the words idle waves poll sit on cache lines of their own
+    kCtlActive = 64,      // waves holding a task
+    kCtlIdle = 96,        // waves waiting for donated tasks
+    kCtlDonHead = 128,    // next donated task to take
+    kCtlDonTail = 160,    // donated-task slots reserved
+    kCtlWords = 192
 };
 
 struct DevGraph {
@@ -69,6 +76,8 @@ struct KArgs {
     uint4* split_items;         // (plan, root, lo, hi); queue q holds [qbase[q], qbase[q+1])
     uint32_t split_cap;
     uint32_t qbase[kQueues + 1];
+    uint32_t* don;              // donated tasks: kDonWords words each
+    uint32_t don_cap;
     uint32_t n_src;             // roots: subset size or n
     const uint32_t* roots;      // subset or NULL (then root i is node i)
     const uint32_t* hubs;       // hub candidates for the split kernel (when roots == NULL)
@@ -95,6 +104,8 @@ struct InitArgs {
     uint32_t* ctl;
     uint32_t* plan_flags;
     unsigned long long* counts;
+    uint32_t* don;              // donated-task slots: their ready words are cleared
+    uint32_t don_cap;
 };
 
 // First-level sub-range length for a root whose first-level list has L1

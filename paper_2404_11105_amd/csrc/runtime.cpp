@@ -96,7 +96,7 @@ int plan_device_desc(xm_plan_t* p, int dev, const PlanDesc** out) {
 struct Layout {
     uint32_t chunk, split, split_work, cap, waves_per_cu, n_waves, n_blocks, e_max, maxc, merge_min;
     bool nonlinear;
-    size_t off_ctl, off_flags, off_table, off_split, off_scratch, total;
+    size_t off_ctl, off_flags, off_table, off_split, off_don, off_scratch, total;
     uint32_t split_cap, wave_words, lds_words;
     uint32_t qbase[xm::kQueues + 1];
 };
@@ -109,6 +109,7 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
                 const xm_count_opts* o, Layout& L) {
     if (!g) return fail(XM_ERR_INVALID, "graph is NULL");
     if (n_plans == 0 || !plans) return fail(XM_ERR_INVALID, "no plans");
+    if (n_plans > 65535) return fail(XM_ERR_INVALID, "at most 65535 plans per launch");
     // struct_size: 0 or at least the layout before roots_host (fields added
     // later are read only when struct_size covers them)
     if (o && o->struct_size != 0 && o->struct_size < offsetof(xm_count_opts, roots_host))
@@ -242,6 +243,8 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
     off = align256(off + (size_t)n_plans * sizeof(PlanDesc));
     L.off_split = off;
     off = align256(off + (size_t)L.split_cap * 16);
+    L.off_don = off;
+    off = align256(off + (size_t)xm::kDonCap * xm::kDonWords * 4);
     L.off_scratch = off;
     off = align256(off + (size_t)L.n_waves * L.wave_words * 4);
     L.total = off;
@@ -284,6 +287,8 @@ int enqueue_count(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const*
     a.plan_flags = reinterpret_cast<uint32_t*>(base + L.off_flags);
     a.split_items = reinterpret_cast<uint4*>(base + L.off_split);
     a.split_cap = L.split_cap;
+    a.don = reinterpret_cast<uint32_t*>(base + L.off_don);
+    a.don_cap = xm::kDonCap;
     for (uint32_t q = 0; q <= xm::kQueues; q++) a.qbase[q] = L.qbase[q];
     a.roots = (o && o->roots_dev) ? o->roots_dev : nullptr;
     a.n_src = a.roots ? o->n_roots : g->n;
@@ -319,6 +324,8 @@ int enqueue_count(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const*
         ia.ctl = a.ctl;
         ia.plan_flags = a.plan_flags;
         ia.counts = a.counts;
+        ia.don = a.don;
+        ia.don_cap = a.don_cap;
         inits.push_back(ia);
     }
     hipEvent_t ev0 = o ? static_cast<hipEvent_t>(o->ev_kernel_start) : nullptr;
