@@ -70,11 +70,8 @@ struct PlanDesc {
     LevelDesc lvl[kMaxK];         // [1..e-1]
     LevelDesc sig[kMaxSig];       // leaf signatures (inj over levels < e)
     uint8_t sig_mult[kMaxSig];    // leaves per signature
-    uint8_t sig_scan[kMaxSig];    // 1: enumerate this signature's base for the union
-    uint8_t sig_implied[kMaxSig]; // membership in sig s implies membership in these (incl. s)
-    uint8_t sig_test[kMaxSig];    // memberships to test for elements of sig s
     uint8_t order[kMaxK];         // level -> pattern vertex (reporting)
-    uint8_t pad2[4];
+    uint8_t pad2[5];
     Term terms[kMaxTerms];
     // Every signature mask M used by a term block, with the candidate test of
     // the intersection of those signatures' sets (union of their constraints):

@@ -471,8 +471,7 @@ std::string plan_json(const Pat& p, const PlanDesc& D, const CoverReport& cr, bo
         if (g) s += ",";
         std::string o = lvl_json(D.sig[g]);
         o.pop_back();
-        std::snprintf(buf, sizeof buf, ",\"mult\":%u,\"scan\":%u,\"implied\":%u,\"test\":%u}", D.sig_mult[g],
-                      D.sig_scan[g], D.sig_implied[g], D.sig_test[g]);
+        std::snprintf(buf, sizeof buf, ",\"mult\":%u}", D.sig_mult[g]);
         o += buf;
         s += o;
     }
@@ -664,17 +663,6 @@ int build_plan(uint32_t k, uint32_t n_arcs, const uint8_t* arcs, uint32_t flags,
         D.sig[g].deg_check = 0;
         if (reduced && D.e >= 2)
             choose_reuse(D, D.sig[g], (int)D.e - 1, (uint32_t)p.dout(v), (uint32_t)p.din(v));
-    }
-    for (uint32_t g = 0; g < D.n_sig; g++) {
-        uint8_t implied = 0;
-        bool scan = true;
-        for (uint32_t h = 0; h < D.n_sig; h++) {
-            if (sigs[h].subset_of(sigs[g])) implied |= (uint8_t)(1u << h);
-            if (h < g && sigs[h].subset_of(sigs[g])) scan = false;
-        }
-        D.sig_implied[g] = implied;
-        D.sig_scan[g] = scan ? 1 : 0;
-        D.sig_test[g] = (uint8_t)(((1u << D.n_sig) - 1) & ~implied);
     }
     std::vector<Term> terms;
     leaf_terms(leaf_sig, terms);

@@ -86,15 +86,28 @@ struct Walker {
             return;
         }
         (void)nb;
-        for (uint32_t s = 0; s < P.n_sig; s++) {
-            if (!P.sig_scan[s]) continue;
+        // one leaf: its signature's lists; several: the lists of every
+        // signature mask the inclusion-exclusion terms measure
+        const uint32_t nd = P.linear ? 1u : P.n_masks;
+        for (uint32_t s = 0; s < nd; s++) {
+            const LevelDesc& L = P.linear ? P.sig[0] : P.mdesc[s];
+            if (!P.linear && L.n_cons == 1 && L.reuse == kNoReuse) {
+                // a single list counts with its length (the kernel reads the
+                // length and searches the list only for the bound nodes)
+                const uint32_t* a;
+                uint32_t l;
+                list(phi[L.cons_lvl[0]], L.cons_dir[0], a, l);
+                w.elements += l;
+                w.fetches += 1;
+                continue;
+            }
             bool fl;
             const uint32_t* base;
             uint32_t blen;
             const uint32_t* probe[kMaxCons];
             uint32_t plen[kMaxCons];
             int np;
-            lists(P.sig[s], fl, base, blen, probe, plen, np);
+            lists(L, fl, base, blen, probe, plen, np);
             w.elements += blen;
             w.fetches += 1;
             for (int i = 0; i < np; i++) {
