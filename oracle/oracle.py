@@ -39,6 +39,9 @@ def _load():
                                   P, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
                                   P, P, P, ctypes.c_int, P]
         lib.xmo_count.restype = ctypes.c_int
+        lib.xmo_list.argtypes = [ctypes.c_uint32, P, P, ctypes.c_int, ctypes.c_int, P,
+                                 P, ctypes.c_uint64, ctypes.c_int, P, ctypes.c_uint64, P, P]
+        lib.xmo_list.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -87,3 +90,26 @@ def count_per_root(graph, pattern, roots=None, mode: str = "A", threads: int = 1
     total, pr, first = _call(graph, pattern, roots, mode, threads, True, root_vertex)
     per = [int(pr[2 * i]) | (int(pr[2 * i + 1]) << 64) for i in range(pr.size // 2)]
     return total, per, first
+
+
+def list_embeddings(graph, pattern, cap: int, roots=None, root_vertex: int = -1):
+    """(total, array [min(total, cap), k] of embeddings): row = phi of pattern
+    vertices 0..k-1, in the oracle's enumeration order."""
+    lib = _load()
+    out_off = np.ascontiguousarray(graph.out_off, dtype=np.uint32)
+    out_adj = np.ascontiguousarray(graph.out_adj, dtype=np.uint32)
+    if out_adj.size == 0:
+        out_adj = np.zeros(1, dtype=np.uint32)
+    arcs = np.frombuffer(pattern.arcs_u8(), dtype=np.uint8).copy()
+    if arcs.size == 0:
+        arcs = np.zeros(2, dtype=np.uint8)
+    r = None if roots is None else np.ascontiguousarray(roots, dtype=np.uint32)
+    nr = 0 if r is None else int(r.size)
+    out = np.zeros((max(cap, 1), pattern.k), dtype=np.uint32)
+    lo, hi = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    rc = lib.xmo_list(graph.n, _ptr(out_off), _ptr(out_adj), pattern.k, len(pattern.arcs), _ptr(arcs),
+                      _ptr(r), nr, int(root_vertex), _ptr(out), int(cap), ctypes.byref(lo), ctypes.byref(hi))
+    if rc != 0:
+        raise ValueError(f"oracle rejected the input (code {rc})")
+    total = lo.value | (hi.value << 64)
+    return total, out[:min(total, cap)]

@@ -30,6 +30,11 @@
  * Threads only split the list of root images (images of the first vertex)
  * for timing; the per-root algorithm is the same.
  *
+ * Listing (xmo_list) walks the same maps in mode A, single-threaded, and
+ * writes each one as phi(0), ..., phi(k-1) in pattern-vertex order (the
+ * embeddings of section 5.3's result generation, written out instead of
+ * counted), up to a capacity; the total is always exact.
+ *
  * The oracle reads only the out-CSR and builds its own sorted in-lists.
  */
 #include <stdint.h>
@@ -134,12 +139,22 @@ typedef struct {
     const oplan *p;
     int mode;
     uint32_t phi[MAXK];
+    /* listing: complete maps go to out[cap][k] (pattern-vertex order) */
+    uint32_t *out;
+    uint64_t cap, listed;
 } ostate;
 
 static u128 extend(ostate *s, int i) {
     const ograph *g = s->g;
     const oplan *p = s->p;
-    if (i == p->k) return 1;
+    if (i == p->k) {
+        if (s->out) {
+            if (s->listed < s->cap)
+                for (int t = 0; t < p->k; t++) s->out[s->listed * (uint64_t)p->k + p->order[t]] = s->phi[t];
+            s->listed++;
+        }
+        return 1;
+    }
     /* candidate list from the first constraint */
     int j0 = p->cons_j[i][0], d0 = p->cons_dir[i][0];
     uint32_t a = s->phi[j0];
@@ -184,6 +199,7 @@ static void *worker(void *arg) {
     oworker *w = (oworker *)arg;
     ostate s;
     s.g = w->g; s.p = w->p; s.mode = w->mode;
+    s.out = NULL; s.cap = s.listed = 0;
     w->sum = 0;
     for (;;) {
         uint64_t base = __atomic_fetch_add(w->cursor, 64, __ATOMIC_RELAXED);
@@ -251,5 +267,38 @@ int xmo_count(uint32_t n, const uint32_t *out_off, const uint32_t *out_adj,
     *total_lo = (uint64_t)total;
     *total_hi = (uint64_t)(total >> 64);
     free(ws); free(tid); free(g.in_off); free(g.in_adj);
+    return 0;
+}
+
+/*
+ * List the embeddings: out (nullable when cap is 0) receives up to cap maps,
+ * k uint32 each, phi of pattern vertex 0..k-1; *total receives the exact
+ * number of embeddings (lo, hi).  roots / root_vertex as in xmo_count.
+ * Returns as xmo_count.
+ */
+int xmo_list(uint32_t n, const uint32_t *out_off, const uint32_t *out_adj,
+             int k, int n_arcs, const uint8_t *arcs,
+             const uint32_t *roots, uint64_t n_roots, int root_vertex,
+             uint32_t *out, uint64_t cap, uint64_t *total_lo, uint64_t *total_hi) {
+    oplan p;
+    int rc = make_plan(k, n_arcs, arcs, root_vertex, &p);
+    if (rc) return rc;
+    ograph g;
+    g.n = n; g.out_off = out_off; g.out_adj = out_adj;
+    if (build_in(&g)) return -3;
+    if (!roots) n_roots = n;
+    ostate s;
+    s.g = &g; s.p = &p; s.mode = 0;
+    s.out = out; s.cap = out ? cap : 0; s.listed = 0;
+    u128 total = 0;
+    for (uint64_t r = 0; r < n_roots; r++) {
+        uint32_t x = roots ? roots[r] : (uint32_t)r;
+        if (x >= n) continue;
+        s.phi[0] = x;
+        total += extend(&s, 1);
+    }
+    *total_lo = (uint64_t)total;
+    *total_hi = (uint64_t)(total >> 64);
+    free(g.in_off); free(g.in_adj);
     return 0;
 }

@@ -33,6 +33,21 @@ def brute_force(graph, pattern) -> int:
     return int(ok.sum())
 
 
+def brute_force_maps(graph, pattern) -> np.ndarray:
+    """Every injective map with every pattern arc on a data arc, one row of
+    phi(0..k-1) per map, rows sorted."""
+    A = adjacency(graph).astype(bool)
+    n, k = graph.n, pattern.k
+    if k > n:
+        return np.zeros((0, k), dtype=np.int64)
+    perms = np.array(list(itertools.permutations(range(n), k)), dtype=np.int64).reshape(-1, k)
+    ok = np.ones(perms.shape[0], dtype=bool)
+    for s, d in pattern.arcs:
+        ok &= A[perms[:, s], perms[:, d]]
+    rows = perms[ok]
+    return rows[np.lexsort(rows.T[::-1])] if rows.size else rows
+
+
 def falling(x: int, s: int) -> int:
     r = 1
     for i in range(s):

@@ -149,3 +149,22 @@ def test_oracle_rejects_bad_patterns():
         oracle.count(g, xmgen.Pattern(3, ((0, 1),)))  # vertex 2 isolated
     with pytest.raises(ValueError):
         oracle.count(g, xmgen.Pattern(2, ((0, 0),)))  # self-loop
+
+
+@pytest.mark.parametrize("name", ["arc", "ffl", "c3", "bifan", "c4", "tt4p", "outstar3"])
+def test_oracle_listing_equals_brute_force_maps(name):
+    """Listing mode writes exactly the set of embeddings brute force finds
+    (pattern-vertex order), and caps without changing the total."""
+    pat = xmgen.named(name)
+    for seed in range(3):
+        g = xmgen.uniform_digraph(9, 30, 40 + seed)
+        want = pins.brute_force_maps(g, pat)
+        total, rows = oracle.list_embeddings(g, pat, cap=10 ** 6)
+        assert total == len(want)
+        got = rows.astype(np.int64)
+        got = got[np.lexsort(got.T[::-1])] if got.size else got
+        assert np.array_equal(got, want)
+        # a small capacity keeps the exact total and writes a subset
+        total2, part = oracle.list_embeddings(g, pat, cap=3)
+        assert total2 == total and len(part) == min(3, total)
+        assert all(any((r == w).all() for w in want) for r in part.astype(np.int64))
