@@ -232,6 +232,18 @@ typedef struct xm_count_opts {
        degrees; without it every subset root is assumed to have the longest
        list in the graph, which can coarsen the hub splits. */
     const uint32_t* roots_host;
+    /* Listing (section 5.3's result generation, written out): when list_dev
+       is non-NULL, every embedding found is also written as k uint32 node
+       ids in pattern-vertex order (row i at list_dev[i*k .. i*k+k)), rows in
+       no particular order, up to list_cap rows; *list_count_dev (device,
+       zeroed by the launch) receives the number of embeddings found, which
+       may exceed list_cap (then only list_cap rows were written).  Needs
+       n_plans = 1 and a plan whose leaf group is a single vertex (every
+       XM_PLAN_UNREDUCED plan); XM_ERR_INVALID otherwise.  Counts are
+       written as usual. */
+    uint32_t* list_dev;
+    uint64_t list_cap;
+    unsigned long long* list_count_dev;
 } xm_count_opts;
 
 size_t xm_workspace_size(const xm_graph_t* g, uint32_t n_plans,

@@ -4,8 +4,8 @@ The compute path is libxminer.so: a host planner plus gfx950 HIP kernels
 behind the C ABI of include/xminer.h.  This package only marshals
 arguments to it; PyTorch supplies device memory and streams.
 """
-from .api import (Graph, Plan, Counter, Watchdog, count, count_anchored, describe_plan, plan_json,
-                  plan_work, workspace_bytes)
+from .api import (Graph, Plan, Counter, Watchdog, count, count_anchored, describe_plan, list_embeddings,
+                  plan_json, plan_work, workspace_bytes)
 
-__all__ = ["Graph", "Plan", "Counter", "Watchdog", "count", "count_anchored", "describe_plan", "plan_json",
-           "plan_work", "workspace_bytes"]
+__all__ = ["Graph", "Plan", "Counter", "Watchdog", "count", "count_anchored", "describe_plan",
+           "list_embeddings", "plan_json", "plan_work", "workspace_bytes"]

@@ -51,6 +51,9 @@ class XmCountOpts(ctypes.Structure):
         ("ev_kernel_start", ctypes.c_void_p),
         ("ev_kernel_stop", ctypes.c_void_p),
         ("roots_host", ctypes.c_void_p),
+        ("list_dev", ctypes.c_void_p),
+        ("list_cap", ctypes.c_uint64),
+        ("list_count_dev", ctypes.c_void_p),
     ]
 
 

@@ -145,7 +145,7 @@ def describe_plan(pattern, reduced: bool = True) -> dict:
 
 
 def make_opts(chunk=0, split=0, cap=0, waves_per_cu=0, roots=None, cancel=None, events=None,
-              merge_min=0, merge_ratio=0, split_work=0, roots_host=None):
+              merge_min=0, merge_ratio=0, split_work=0, roots_host=None, listing=None):
     """xm_count_opts; roots is a device tensor, roots_host (optional) a
     contiguous uint32 numpy copy the caller keeps alive."""
     o = _lib.XmCountOpts()
@@ -159,6 +159,11 @@ def make_opts(chunk=0, split=0, cap=0, waves_per_cu=0, roots=None, cancel=None, 
             o.roots_host = roots_host.ctypes.data
     if cancel is not None:
         o.cancel_dev = cancel.data_ptr()
+    if listing is not None:
+        buf, cap_rows, cnt = listing
+        o.list_dev = buf.data_ptr()
+        o.list_cap = int(cap_rows)
+        o.list_count_dev = cnt.data_ptr()
     if events is not None:
         o.ev_kernel_start = events[0].cuda_event
         o.ev_kernel_stop = events[1].cuda_event
@@ -174,7 +179,7 @@ class Counter:
 
     def __init__(self, graph: Graph, plans, chunk=0, split=0, cap=0, waves_per_cu=0,
                  roots=None, cancel=None, kernel_events: bool = False, stream=None,
-                 merge_min=0, merge_ratio=0, split_work=0, workspace=None):
+                 merge_min=0, merge_ratio=0, split_work=0, workspace=None, list_cap: int = 0):
         import torch
         self.graph = graph
         self.plans = list(plans)
@@ -192,8 +197,16 @@ class Counter:
                 self.events = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
                 for ev in self.events:
                     ev.record(s)
+        self.list = self.list_count = None
+        listing = None
+        if list_cap > 0:
+            # every embedding written out: rows of k node ids (one plan, one leaf)
+            k = self.plans[0].pattern.k
+            self.list = torch.empty(int(list_cap) * k, dtype=torch.int32, device=dev)
+            self.list_count = torch.zeros(1, dtype=torch.int64, device=dev)
+            listing = (self.list, int(list_cap), self.list_count)
         self.opts = make_opts(chunk, split, cap, waves_per_cu, self.roots, cancel, self.events,
-                              merge_min, merge_ratio, split_work, self.roots_host)
+                              merge_min, merge_ratio, split_work, self.roots_host, listing)
         self._parr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
         ws = lib().xm_workspace_size(graph.handle, len(self.plans), self._parr, ctypes.byref(self.opts))
         if ws == 0:
@@ -229,7 +242,7 @@ class Counter:
         key = stream.cuda_stream
         if key not in self._streams:
             self._streams.add(key)
-            for t in (self.workspace, self.counts, self.status, self.roots):
+            for t in (self.workspace, self.counts, self.status, self.roots, self.list, self.list_count):
                 if t is not None:
                     t.record_stream(stream)
 
@@ -266,6 +279,14 @@ class Counter:
         st = self.status.cpu().numpy()
         out = [int(c[2 * i]) | (int(c[2 * i + 1]) << 64) for i in range(len(self.plans))]
         return out, [int(s) for s in st]
+
+    def listed(self):
+        """(number of embeddings found, array [min(found, list_cap), k] of rows in
+        pattern-vertex order) after a listing launch completed."""
+        n = int(self.list_count.cpu().numpy().view(np.uint64)[0])
+        k = self.plans[0].pattern.k
+        rows = self.list.cpu().numpy().view(np.uint32).reshape(-1, k)
+        return n, rows[:min(n, rows.shape[0])]
 
     def kernel_ms(self) -> float:
         """Duration of the last count kernel (call after the stream completed)."""
@@ -373,6 +394,22 @@ def count_anchored(graph: Graph, pattern, vertex: int, nodes, reduced: bool = Tr
         check(status[0])
         out.append(counts[0])
     return out
+
+
+def list_embeddings(graph: Graph, pattern, cap: int, reduced: bool = False, roots=None, root_vertex=None,
+                    stream=None, **opts):
+    """Write out the embeddings of `pattern`: (total found, array [min(total,
+    cap), k] of node ids in pattern-vertex order, rows in no particular
+    order).  The plan is unreduced by default (its last vertex is the only
+    leaf); a reduced plan works when its leaf group is one vertex."""
+    plan = Plan(pattern, reduced=reduced, graph=graph, root_vertex=root_vertex)
+    c = Counter(graph, [plan], roots=roots, list_cap=cap, **opts)
+    c.run(stream)
+    counts, status = c.results()
+    check(status[0])
+    n, rows = c.listed()
+    assert n == counts[0]
+    return n, rows
 
 
 def count(graph: Graph, plans, stream=None, **opts):

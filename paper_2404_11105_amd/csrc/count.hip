@@ -695,6 +695,29 @@ __device__ void leaf_masks(Ctx& C, uint32_t nb, uint32_t p, bool pv) {
     wave_sync();
 }
 
+// Listing: the survivors of a tile pair are whole embeddings (bound levels
+// 0..nb-1 of their parent plus the leaf); one 64-bit atomic per step reserves
+// their rows, written in pattern-vertex order while they fit the capacity.
+__device__ __forceinline__ void write_rows(const Ctx& C, uint32_t nb, uint64_t ma, uint64_t mb, uint32_t ja,
+                                           uint32_t xa, bool oka, uint32_t jb, uint32_t xb, bool okb) {
+    const KArgs& a = *C.a;
+    const uint32_t na = (uint32_t)__popcll(ma), nbb = (uint32_t)__popcll(mb);
+    if (na + nbb == 0) return;
+    unsigned long long base = 0;
+    if (C.lane == 0) base = atomicAdd(a.list_count, (unsigned long long)(na + nbb));
+    base = __shfl(base, 0, 64);
+    const PlanDesc* P = C.P;
+    const uint32_t k = P->k;
+    auto put = [&](unsigned long long row, uint32_t j, uint32_t x) {
+        if (row >= a.list_cap) return;
+        uint32_t* out = a.list + row * k;
+        for (uint32_t l = 0; l < nb; l++) out[P->order[l]] = C.s.bound[l * 64 + j];
+        out[P->order[nb]] = x;
+    };
+    if (oka) put(base + rank_below(ma), ja, xa);
+    if (okb) put(base + na + rank_below(mb), jb, xb);
+}
+
 // Count the leaf group for every partial match in level `lv` (= e - 1).
 template <bool NONLIN>
 __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
@@ -723,7 +746,8 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
             leaf_masks(C, nb, p, pv);
             continue;
         }
-        if (linear && S0.n_cons == 1 && S0.reuse == kNoReuse) {
+        const bool listing = a.list != nullptr;
+        if (!listing && S0.n_cons == 1 && S0.reuse == kNoReuse) {
             // one leaf drawn from one list L: |L| minus the bound nodes found in L
             uint32_t v = 0;
             if (pv) {
@@ -752,7 +776,7 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
             uint32_t probe_c = kSkip;
             bool big = false;
             const uint32_t ns = n_slots(S);
-            if (linear && pv) {
+            if (linear && pv && !listing) {
                 uint32_t nprobe = 0;
                 for (uint32_t c = 0; c < ns; c++)
                     if (C.s.slot_len[c * 64 + lane] != kSkip) {
@@ -787,13 +811,16 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
                 uint32_t xa = 0, xb = 0;
                 if (oka) xa = base_elem(C, ja, la);
                 if (okb) xb = base_elem(C, jb, lb);
-                // injectivity is settled per partial match below
-                check_pair(C, S, 0u, nb, ns, ja, xa, oka, jb, xb, okb);
+                // injectivity is settled per partial match below (per element
+                // when every embedding is written out)
+                check_pair(C, S, listing ? S.inj : 0u, nb, ns, ja, xa, oka, jb, xb, okb);
                 // one leaf: survivors are only counted
-                lin += (unsigned long long)(__popcll(__ballot(oka)) + __popcll(__ballot(okb)));
+                const uint64_t ma = __ballot(oka), mb = __ballot(okb);
+                lin += (unsigned long long)(__popcll(ma) + __popcll(mb));
+                if (listing) write_rows(C, nb, ma, mb, ja, xa, oka, jb, xb, okb);
             }
             // bound nodes the leaf may not take were counted if they are in the set
-            for (uint32_t b = 0; b < nb; b++) {
+            for (uint32_t b = 0; b < nb && !listing; b++) {
                 if (!((S.inj >> b) & 1u)) continue;
                 const bool hit = pv && !big && bound_in_set(C, ns, C.s.bound[b * 64 + lane]);
                 lin -= (unsigned long long)__popcll(__ballot(hit));
@@ -1165,6 +1192,7 @@ __global__ void init_kernel(InitArgs a) {
         // the workspace is reused across launches (and by the caller's
         // allocator): a slot is ready only once this launch publishes it
         for (uint32_t i = tid; i < a.don_cap; i += nthr) a.don[(uint64_t)i * kDonWords + 1] = 0;
+        if (a.list_count && tid == 0) *a.list_count = 0;
     }
 }
 

@@ -78,6 +78,9 @@ struct KArgs {
     uint32_t qbase[kQueues + 1];
     uint32_t* don;              // donated tasks: kDonWords words each
     uint32_t don_cap;
+    uint32_t* list;             // listing: rows of k node ids (NULL: counting only)
+    unsigned long long* list_count;
+    unsigned long long list_cap;
     uint32_t n_src;             // roots: subset size or n
     const uint32_t* roots;      // subset or NULL (then root i is node i)
     const uint32_t* hubs;       // hub candidates for the split kernel (when roots == NULL)
@@ -106,6 +109,7 @@ struct InitArgs {
     unsigned long long* counts;
     uint32_t* don;              // donated-task slots: their ready words are cleared
     uint32_t don_cap;
+    unsigned long long* list_count;  // listing counter (NULL: none)
 };
 
 // First-level sub-range length for a root whose first-level list has L1

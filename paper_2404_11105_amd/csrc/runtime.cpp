@@ -114,9 +114,17 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
     // later are read only when struct_size covers them)
     if (o && o->struct_size != 0 && o->struct_size < offsetof(xm_count_opts, roots_host))
         return fail(XM_ERR_INVALID, "xm_count_opts.struct_size too small");
+    const bool full_opts = o && (o->struct_size == 0 || o->struct_size >= sizeof(xm_count_opts));
     const uint32_t* roots_host =
-        (o && o->roots_dev && (o->struct_size == 0 || o->struct_size >= sizeof(xm_count_opts))) ? o->roots_host
-                                                                                               : nullptr;
+        (o && o->roots_dev && (o->struct_size == 0 || o->struct_size >= offsetof(xm_count_opts, list_dev)))
+            ? o->roots_host
+            : nullptr;
+    if (full_opts && o->list_dev) {
+        if (n_plans != 1) return fail(XM_ERR_INVALID, "listing needs exactly one plan");
+        if (!plans[0] || plans[0]->desc.t != 1)
+            return fail(XM_ERR_INVALID, "listing needs a plan whose leaf group is one vertex (e.g. unreduced)");
+        if (!o->list_count_dev) return fail(XM_ERR_INVALID, "listing needs list_count_dev");
+    }
     L.chunk = (o && o->chunk) ? o->chunk : 0;  // 0: sized below from the task count
     L.split = (o && o->split) ? o->split : 64;
     L.split_work = (o && o->split_work) ? o->split_work : 4096;
@@ -305,6 +313,10 @@ int enqueue_count(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const*
     a.counts = reinterpret_cast<unsigned long long*>(counts);
     a.status = status;
     a.cancel = o ? o->cancel_dev : nullptr;
+    const bool listing = o && (o->struct_size == 0 || o->struct_size >= sizeof(xm_count_opts)) && o->list_dev;
+    a.list = listing ? o->list_dev : nullptr;
+    a.list_count = listing ? o->list_count_dev : nullptr;
+    a.list_cap = listing ? o->list_cap : 0;
 
     std::vector<xm::InitArgs> inits;
     for (uint32_t first = 0; first < n_plans; first += xm::kMaxPlansPerInit) {
@@ -326,6 +338,7 @@ int enqueue_count(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const*
         ia.counts = a.counts;
         ia.don = a.don;
         ia.don_cap = a.don_cap;
+        ia.list_count = a.list_count;
         inits.push_back(ia);
     }
     hipEvent_t ev0 = o ? static_cast<hipEvent_t>(o->ev_kernel_start) : nullptr;

@@ -212,3 +212,44 @@ def test_root_deciles_sum_to_full_counts(xa):
         assert st == [0] * len(plans)
         sums = [a + b for a, b in zip(sums, got)]
     assert sums == want
+
+
+def _sorted_rows(a):
+    a = np.asarray(a, dtype=np.int64)
+    return a[np.lexsort(a.T[::-1])] if a.size else a.reshape(0, a.shape[1] if a.ndim == 2 else 0)
+
+
+def test_listing_equals_oracle_embeddings(xa):
+    """Listing mode: the rows written are exactly the oracle's embeddings
+    (pattern-vertex order), with the exact total, for unreduced plans and a
+    reduced plan whose leaf group is one vertex; a small capacity keeps the
+    total and writes distinct true embeddings."""
+    banner("listing: uniform 60/400 and rmat 6, unreduced and one-leaf reduced plans")
+    for g in (xmgen.uniform_digraph(60, 400, 12), xmgen.rmat(6, seed=8)):
+        G = xa.Graph(g)
+        for name in ["arc", "ffl", "c3", "bifan", "c4", "tt4p", "c5chord"]:
+            p = xmgen.named(name)
+            total, want = oracle.list_embeddings(g, p, cap=2_000_000)
+            assert total == len(want)
+            for reduced in (False, True):
+                if reduced and xa.Plan(p).describe()["t"] != 1:
+                    continue
+                n, rows = xa.list_embeddings(G, p, cap=2_000_000, reduced=reduced)
+                assert n == total and len(rows) == total, (name, reduced)
+                assert np.array_equal(_sorted_rows(rows), _sorted_rows(want)), (name, reduced)
+        p = xmgen.named("c4")
+        total = oracle.count(g, p)
+        if total > 10:
+            n, rows = xa.list_embeddings(G, p, cap=10)
+            assert n == total and len(rows) == 10
+            allw = {tuple(r) for r in oracle.list_embeddings(g, p, cap=2_000_000)[1].tolist()}
+            got = [tuple(r) for r in rows.tolist()]
+            assert len(set(got)) == 10 and all(r in allw for r in got)
+
+
+def test_listing_rejects_multi_leaf_plans(xa):
+    banner("listing needs one plan with a one-vertex leaf group")
+    g = xmgen.uniform_digraph(60, 400, 12)
+    G = xa.Graph(g)
+    with pytest.raises(Exception):
+        xa.list_embeddings(G, xmgen.named("outstar3"), cap=100, reduced=True)
