@@ -271,6 +271,60 @@ def bench_fraction(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_listing(args):
+    """Listing mode on the R-MAT scale 16 graph: the unreduced plans of the
+    feed-forward triangle and the 3-cycle write every embedding (3 node ids
+    each) into HBM; rows/s and bytes written/s, against the counting launch of
+    the same plans, and the rows checked against the oracle's listing on a
+    seeded root sample."""
+    import numpy as np
+    import torch
+
+    import oracle
+    import xmgen
+    from paper_2404_11105_amd import Counter, Graph, Plan
+
+    torch.cuda.set_device(0)
+    log("[listing] generating R-MAT scale 16")
+    g = xmgen.rmat(16, seed=0)
+    G = Graph(g)
+    s = torch.cuda.Stream()
+    out = []
+    for name in ("ffl", "c3"):
+        p = xmgen.named(name)
+        plan = Plan(p, reduced=False, graph=G)
+        cnt = Counter(G, [plan])
+        cnt.capture(s)
+        ms_count, _ = timed_steps(cnt, s, max(3, args.steps // 4), 1)
+        total = cnt.results()[0][0]
+        lst = Counter(G, [plan], list_cap=total)
+        lst.capture(s)
+        ms_list, _ = timed_steps(lst, s, max(3, args.steps // 4), 1)
+        n, rows = lst.listed()
+        assert n == total
+        # oracle parity on the rows of a seeded root sample
+        roots = np.sort(np.random.default_rng(3).choice(g.n, size=2048, replace=False)).astype(np.uint32)
+        rv = plan.root_vertex
+        sub = Counter(G, [Plan(p, reduced=False, graph=G, root_vertex=rv)], roots=roots, list_cap=total)
+        sub.run(s)
+        sn, srows = sub.listed()
+        on, orows = oracle.list_embeddings(g, p, cap=total, roots=roots, root_vertex=rv)
+        key = lambda a: a[np.lexsort(a.astype(np.int64).T[::-1])]  # noqa: E731
+        same = sn == on and np.array_equal(key(srows), key(orows))
+        log(f"[listing] {name}: {n} rows, {ms_list:.2f} ms listing vs {ms_count:.2f} ms counting")
+        out.append({"pattern": name, "rows": str(n), "ms_listing": round(ms_list, 3),
+                    "ms_counting": round(ms_count, 3), "rows_per_s": n / (ms_list / 1e3),
+                    "bytes_written_per_s": n * 3 * 4 / (ms_list / 1e3),
+                    "oracle_rows_equal_on_root_sample": bool(same), "sample_rows": str(sn)})
+    rows_total = sum(int(o["rows"]) for o in out)
+    ms_total = sum(o["ms_listing"] for o in out)
+    rec = {"metric": METRIC, "value": rows_total / (ms_total / 1e3), "unit": "embeddings listed/s", "n_gpus": 1,
+           "steps": max(3, args.steps // 4), "warmup": 1, "ms_per_step": round(ms_total, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+           "data": "synthetic", "config": {"workload": "rmat16_listing_ffl_c3_unreduced"}, "patterns": out}
+    print(json.dumps(rec), flush=True)
+
+
 def bench_serve(args):
     """Continuous batching over 8 resident R-MAT graphs (scales 18-24, built
     on the device); Poisson arrivals at two fixed rates set from the measured
@@ -378,7 +432,8 @@ def main():
                     help="shortest list with a dense membership row (default: the library's)")
     ap.add_argument("--dense-rows", type=int, default=None,
                     help="byte budget of the dense rows (0: none; default: the library's)")
-    ap.add_argument("--workload", default="rmat16", choices=["rmat16", "batch256", "serve", "fraction"],
+    ap.add_argument("--workload", default="rmat16",
+                    choices=["rmat16", "batch256", "serve", "fraction", "listing"],
                     help="rmat16: the contract line (default); batch256 / serve: the batched "
                          "and serving workloads, each printing its own JSON line")
     ap.add_argument("--requests", type=int, default=150, help="serve: requests per load level and policy")
@@ -402,6 +457,9 @@ def main():
         return
     if args.workload == "fraction":
         bench_fraction(args)
+        return
+    if args.workload == "listing":
+        bench_listing(args)
         return
 
     import numpy as np

@@ -280,9 +280,12 @@ class Counter:
         out = [int(c[2 * i]) | (int(c[2 * i + 1]) << 64) for i in range(len(self.plans))]
         return out, [int(s) for s in st]
 
-    def listed(self):
+    def listed(self, sync: bool = True):
         """(number of embeddings found, array [min(found, list_cap), k] of rows in
-        pattern-vertex order) after a listing launch completed."""
+        pattern-vertex order); sync waits for the device first."""
+        import torch
+        if sync:
+            torch.cuda.synchronize(self.graph.device)
         n = int(self.list_count.cpu().numpy().view(np.uint64)[0])
         k = self.plans[0].pattern.k
         rows = self.list.cpu().numpy().view(np.uint32).reshape(-1, k)
