@@ -65,13 +65,20 @@ class Graph:
                             self.DEFAULT_ROW_MIN if row_min is None else row_min, stream)
 
     def set_dense_rows(self, max_bytes: int, row_min: int = 32, stream=None) -> int:
-        """(Re)build dense rows within max_bytes; returns the threshold used (0: none)."""
+        """(Re)build dense rows within max_bytes; returns the threshold used (0:
+        none).  When the device cannot hold them the budget is halved until it
+        can (rows only make membership tests faster)."""
         import torch
         t = ctypes.c_uint32()
+        budget = int(max_bytes)
         with torch.cuda.device(self.device):
-            check(lib().xm_graph_dense_rows(self.handle, int(max_bytes), int(row_min), _stream_ptr(stream),
-                                            ctypes.byref(t)))
-        return t.value
+            while True:
+                rc = lib().xm_graph_dense_rows(self.handle, budget, int(row_min), _stream_ptr(stream),
+                                               ctypes.byref(t))
+                if rc != _lib.XM_ERR_OOM or budget == 0:
+                    check(rc)
+                    return t.value
+                budget //= 2
 
     def dense_rows_info(self) -> dict:
         t, no, ni, b = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint64()

@@ -1,10 +1,15 @@
 """A host model of the count kernel's control flow (test infrastructure).
 
-It follows count.hip step by step (root chunks and split items, windowed
-level expansion with partial windows, child segments, reuse with fallback,
-leaf-group counting) on numpy arrays, one simulated wave at a time, so that
+It follows count.hip's per-task logic (split items and strided root chunks,
+windowed level expansion with partial windows, child segments, reuse with
+fallback, leaf-group counting: single-signature passes and per-mask
+intersection sizes) on numpy arrays, one simulated wave at a time, so that
 termination, cursor arithmetic and buffer bounds can be checked on the CPU
-for any tuning.  It asserts every buffer index it uses.
+for any tuning.  It asserts every buffer index it uses.  It runs the tasks in
+order on one wave: the XCD-local split queues, work donation between waves
+and the dense-row representation of probe lists change which wave does a
+task and how a membership is tested, not what a task computes, and are not
+modelled.
 """
 from __future__ import annotations
 
