@@ -4,9 +4,11 @@
 Workload (default): R-MAT scale 16 (65,536 nodes, ~955K arcs after removing
 repeats and loops, (a,b,c,d) = (.57,.19,.19,.05), seed 0), uint32 out+in CSR
 resident in HBM, and four patterns: feed-forward triangle, directed 3-cycle,
-bi-fan, directed 4-cycle.  One step counts all four with their reduced plans
-in one persistent launch, replayed as a HIP graph.  The same step is also
-timed as plain per-pattern launches and with unreduced plans.
+bi-fan, directed 4-cycle.  One step counts all four with their reduced,
+symmetry-broken plans (one embedding per automorphism orbit, scaled by the
+orbit size: the same labelled counts) in one persistent launch, replayed as a
+HIP graph.  The same step is also timed without symmetry breaking, as plain
+per-pattern launches and with unreduced plans.
 
 Prints one JSON line (see the repository's benchmark contract).  Only the
 `cpu_baseline` leg calls the oracle, on a bounded root sample.
@@ -122,13 +124,14 @@ def cpu_baseline(g, pats, target_s=4.0):
                       f"), {total_c} embeddings in {total_t:.2f} s"}
 
 
-def traffic_from_profile(n_launch_plans):
+def traffic_from_profile(workload):
     path = os.path.join(ROOT, "profiles", "count_kernel_rmat16_traffic.json")
     if not os.path.exists(path):
         return None
     try:
         rec = json.load(open(path))
-        if rec.get("lib_sha256_16") != lib_hash():
+        # counters of this build and this workload only
+        if rec.get("lib_sha256_16") != lib_hash() or rec.get("workload_id") != workload:
             return None
         return rec.get("hbm_bytes_per_launch")
     except Exception:
@@ -424,6 +427,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip plain/unreduced timings")
+    ap.add_argument("--no-symmetry", action="store_true",
+                    help="plans without symmetry breaking (every embedding enumerated)")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--split", type=int, default=0)
     ap.add_argument("--cap", type=int, default=0)
@@ -474,11 +479,14 @@ def main():
     pats = [xmgen.named(n) for n in PATTERNS]
     G = Graph(g, dense_rows=args.dense_rows, row_min=args.row_min)
     tune = dict(chunk=args.chunk, split=args.split, cap=args.cap, waves_per_cu=args.waves_per_cu)
-    red = [Plan(p, reduced=True, graph=G) for p in pats]
-    unred = [Plan(p, reduced=False, graph=G) for p in pats]
+    sym = not args.no_symmetry
+    red = [Plan(p, reduced=True, graph=G, symmetry=sym) for p in pats]
+    unred = [Plan(p, reduced=False, graph=G, symmetry=sym) for p in pats]
+    workload = "rmat16_ffl_c3_bifan_c4_reduced" + ("_sym" if sym else "") + "_batched"
     s = torch.cuda.Stream()
 
-    # algorithmic work of the four reduced plans (host walk, untimed)
+    # algorithmic work of the four plans (host walk, untimed; with symmetry
+    # breaking only the list parts above each bound count)
     log("[bench] algorithmic work (host walk)")
     threads = max(1, min(16, len(os.sched_getaffinity(0))))
     st = [plan_work(g, p, threads=threads) for p in red]
@@ -505,12 +513,20 @@ def main():
         ms_unred, kern_unred = timed_steps(cu, s, max(3, args.steps // 4), 1)
         assert cu.results()[0] == counts
         E_un = sum(plan_work(g, p, threads=threads)["elements"] for p in unred)
-        extras = {"plain_ms_per_step": round(ms_plain, 4),
+        if sym:
+            log("[bench] batched reduced without symmetry breaking")
+            cn = Counter(G, [Plan(p, reduced=True, graph=G) for p in pats], **tune)
+            cn.capture(s)
+            ms_nosym, _ = timed_steps(cn, s, max(3, args.steps // 4), 1)
+            assert cn.results()[0] == counts
+            extras = {"no_symmetry_ms_per_step": round(ms_nosym, 4),
+                      "symmetry_speedup": round(ms_nosym / ms_step, 3)}
+        extras.update({"plain_ms_per_step": round(ms_plain, 4),
                   "batched_vs_plain_speedup": round(ms_plain / ms_step, 3),
                   "unreduced_ms_per_step": round(ms_unred, 4),
                   "unreduced_kernel_ms": round(kern_unred, 4),
                   "reduced_vs_unreduced_speedup": round(ms_unred / ms_step, 3),
-                  "unreduced_elements": E_un}
+                  "unreduced_elements": E_un})
 
     gold_ok = None
     gpath = os.path.join(ROOT, "tests", "golden", "rmat16.json")
@@ -521,7 +537,7 @@ def main():
     total = sum(counts)
     value = total / (ms_step / 1e3)
     achieved = B_alg / (kern_ms / 1e3) / 1e9
-    traffic = traffic_from_profile(len(pats))
+    traffic = traffic_from_profile(workload)
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] oracle cpu baseline")
@@ -540,9 +556,10 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "rmat16_ffl_c3_bifan_c4_reduced_batched",
+        "config": {"workload": workload,
                    "graph": "R-MAT scale 16, edge factor 16, (.57,.19,.19,.05), seed 0",
-                   "n": g.n, "m": g.m, "patterns": PATTERNS, "plan": "reduced",
+                   "n": g.n, "m": g.m, "patterns": PATTERNS,
+                   "plan": "reduced, symmetry breaking" if sym else "reduced",
                    "launch": "one persistent launch for 4 patterns, HIP graph replay",
                    "parallelism": "1 GPU", "dense_rows": G.dense_rows_info()},
         "counts": [str(c) for c in counts],

@@ -105,14 +105,22 @@ class Graph:
 
 
 class Plan:
-    """A counting plan for one pattern (reduced or unreduced)."""
+    """A counting plan for one pattern (reduced or unreduced).
+
+    symmetry=True counts one embedding per orbit of the pattern's
+    automorphisms on the enumerated vertices and scales the total by the orbit
+    size (same counts, less work); such a plan cannot count a root subset or
+    list embeddings."""
 
     def __init__(self, pattern, reduced: bool = True, graph: Graph | None = None,
-                 root_vertex: int | None = None):
+                 root_vertex: int | None = None, symmetry: bool = False):
         self.pattern = pattern
         self.reduced = reduced
+        self.symmetry = symmetry
         arcs = (ctypes.c_uint8 * max(1, 2 * len(pattern.arcs)))(*pattern.arcs_u8())
         flags = _lib.XM_PLAN_REDUCED if reduced else _lib.XM_PLAN_UNREDUCED
+        if symmetry:
+            flags |= _lib.XM_PLAN_SYMMETRY
         if root_vertex is not None:
             flags |= _lib.XM_PLAN_ROOT(root_vertex)
         h = ctypes.c_void_p()
@@ -147,8 +155,8 @@ def plan_json(plan: Plan) -> str:
     return buf.value.decode()
 
 
-def describe_plan(pattern, reduced: bool = True) -> dict:
-    return Plan(pattern, reduced).describe()
+def describe_plan(pattern, reduced: bool = True, symmetry: bool = False) -> dict:
+    return Plan(pattern, reduced, symmetry=symmetry).describe()
 
 
 def make_opts(chunk=0, split=0, cap=0, waves_per_cu=0, roots=None, cancel=None, events=None,

@@ -123,7 +123,7 @@ __device__ __forceinline__ const uint32_t* safe_ptr(const DevGraph& g) {
 
 // Per-level constraint fields, loaded once into scalar registers.
 struct LK {
-    uint32_t n_cons, reuse, inj, deg_check, extra, dirm, dmin_out, dmin_in;
+    uint32_t n_cons, reuse, inj, deg_check, extra, dirm, dmin_out, dmin_in, gt;
     uint64_t lvlb;
     __device__ __forceinline__ uint32_t lvl(uint32_t c) const { return (uint32_t)(lvlb >> (3 * c)) & 7u; }
     __device__ __forceinline__ uint32_t dir(uint32_t c) const { return (dirm >> c) & 1u; }
@@ -143,6 +143,7 @@ __device__ __forceinline__ LK load_lk(const LevelDesc& D, const KArgs& a) {
     k.dirm = uni(D.dir_mask);
     k.dmin_out = uni(D.dmin_out);
     k.dmin_in = uni(D.dmin_in);
+    k.gt = uni(D.gt);
     k.lvlb = ((uint64_t)uni((uint32_t)(D.lvl_bits >> 32)) << 32) | uni((uint32_t)D.lvl_bits);
     return k;
 }
@@ -239,6 +240,33 @@ __device__ __forceinline__ uint32_t level1_len(const DevGraph& g, const PlanDesc
     return best;
 }
 
+// Largest bound image among the levels in gt (levels < lv) of this lane's
+// partial match.
+__device__ __forceinline__ uint32_t lower_bound_of(const Lds& s, uint32_t gt, uint32_t lv, uint32_t lane) {
+    uint32_t lb = 0;
+    for (uint32_t l = 0; l < lv; l++)
+        if ((gt >> l) & 1u) {
+            const uint32_t b = s.bound[l * 64 + lane];
+            lb = b > lb ? b : lb;
+        }
+    return lb;
+}
+
+// Number of elements <= x in the sorted list a[0, n).
+__device__ __forceinline__ uint32_t count_le(const uint32_t* __restrict__ a, uint32_t n, uint32_t x) {
+    uint32_t lo = 0;
+    while (n > 0) {
+        const uint32_t h = n >> 1;
+        if (a[lo + h] <= x) {
+            lo += h + 1;
+            n -= h + 1;
+        } else {
+            n = h;
+        }
+    }
+    return lo;
+}
+
 // Phase A of a level: lane = one partial match (parent) of the window.  Walks
 // the parent chain into LDS (bound nodes, ancestor indices), picks the base
 // list and writes the probes (the other constraint lists, long ones as their
@@ -326,6 +354,14 @@ __device__ uint32_t phase_a(Ctx& C, const LK& D, uint32_t lv, uint32_t p, bool p
         }
     }
     for (; k < D.n_cons; k++) put(k, safe_ptr(g), kSkip);
+    if (D.gt) {
+        // symmetry breaking: only candidates above the largest image of the
+        // levels in gt; the base is sorted, so they are a suffix of it
+        const uint32_t lb = lower_bound_of(C.s, D.gt, lv, lane);
+        const uint32_t skip = count_le(base, len, lb);
+        base += skip;
+        len -= skip;
+    }
     const uint64_t bv = reinterpret_cast<uint64_t>(base);
     C.s.base_lo[lane] = (uint32_t)bv;
     C.s.base_hi[lane] = (uint32_t)(bv >> 32);
@@ -757,6 +793,12 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
                 uint32_t o = off[nd];
                 uint32_t l = off[nd + 1] - o;
                 const uint32_t* L = adj_of(g, S0.dir(0)) + o;
+                if (S0.gt) {
+                    // symmetry breaking: the suffix above the bound
+                    const uint32_t skip = count_le(L, l, lower_bound_of(C.s, S0.gt, nb, lane));
+                    L += skip;
+                    l -= skip;
+                }
                 v = l;
                 for (uint32_t b = 0; b < nb; b++)
                     if (((S0.inj >> b) & 1u) && contains(L, l, C.s.bound[b * 64 + lane])) v -= 1;
@@ -1204,6 +1246,16 @@ __global__ void finalize_kernel(KArgs a) {
         else if (a.ctl[kCtlQueueFull]) st = -6;
         else if (a.ctl[kCtlCancelled]) st = -7;
         else if (a.plan_flags[i] & 1u) st = -5;
+        const uint32_t m = a.plans[i].sym_mult;
+        if (m > 1 && st == 0) {
+            // one embedding per orbit was counted: scale the 128-bit total
+            unsigned long long* c = a.counts + 2 * i;
+            const unsigned __int128 lo = (unsigned __int128)c[0] * m;
+            const unsigned __int128 hi = (unsigned __int128)c[1] * m + (unsigned long long)(lo >> 64);
+            if (hi >> 64) st = -5;
+            c[0] = (unsigned long long)lo;
+            c[1] = (unsigned long long)hi;
+        }
         a.status[i] = st;
     }
 }

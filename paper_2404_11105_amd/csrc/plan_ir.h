@@ -23,6 +23,17 @@
 // level r under the same ancestors (section 5.2 intermediate-result reuse: an
 // included constraint is materialised from the including one's result) and
 // checks only the constraints in `extra`.
+//
+// Symmetry breaking (the symmetry destruction of the related-work section,
+// made exact): with H the automorphisms of the pattern that map the
+// conditioned vertices (the enumerated levels, plus the leaf when the leaf
+// group is one vertex) onto themselves, H acts freely on the partial matches
+// of those vertices and leaves the number of completions unchanged.  A
+// stabiliser chain of H, taken in level order, gives conditions
+// phi(v_j) < phi(v_i) (j earlier than i) that exactly one partial match of
+// every H-orbit meets; the plan counts those and scales by |H| restricted to
+// the conditioned vertices (sym_mult).  Only a lower bound arises per level:
+// the largest image among the levels in `gt`.
 #pragma once
 #include <stdint.h>
 
@@ -48,6 +59,8 @@ struct LevelDesc {
     uint8_t cons_dir[kMaxCons];   // 0: out(phi(v_j)), 1: in(phi(v_j))
     uint32_t dmin_out, dmin_in;
     uint64_t lvl_bits;            // cons_lvl[c] at bits [3c, 3c+3) (packed copy)
+    uint8_t gt;                   // bit j: keep only candidates x > phi(v_j) (symmetry breaking)
+    uint8_t pad[7];
 };
 
 struct Term {
@@ -66,7 +79,7 @@ struct PlanDesc {
     uint32_t t;                   // leaves
     uint32_t linear;              // 1: one leaf -> the count is a plain sum of set sizes
     uint32_t n_terms;
-    uint32_t pad1;
+    uint32_t sym_mult;            // >1: the plan counts one embedding per orbit of this size
     LevelDesc lvl[kMaxK];         // [1..e-1]
     LevelDesc sig[kMaxSig];       // leaf signatures (inj over levels < e)
     uint8_t sig_mult[kMaxSig];    // leaves per signature

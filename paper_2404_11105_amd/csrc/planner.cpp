@@ -19,6 +19,7 @@
 //   unreduced - every level materialises all of its constraints from the data
 //               graph; only the last vertex is counted instead of enumerated.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -426,6 +427,87 @@ void choose_reuse(PlanDesc& D, LevelDesc& L, int max_src_level, uint32_t need_ou
     D.seg_src |= 1u << best;
 }
 
+// ---------------------------------------------------------------------------
+// Symmetry breaking over the conditioned vertices (the enumerated levels, and
+// the leaf when the leaf group is one vertex).
+// ---------------------------------------------------------------------------
+using Perm = std::array<uint8_t, kMaxK>;
+
+// All automorphisms of the pattern (arc-preserving permutations), by brute
+// force over the at most 7! permutations.
+std::vector<Perm> automorphisms(const Pat& p) {
+    std::vector<Perm> out;
+    Perm s{};
+    for (int i = 0; i < p.k; i++) s[i] = (uint8_t)i;
+    do {
+        bool ok = true;
+        for (int a = 0; a < p.k && ok; a++) {
+            uint32_t img = 0;
+            for (int b = 0; b < p.k; b++)
+                if (p.out[a] & (1u << b)) img |= 1u << s[b];
+            ok = img == p.out[s[a]];
+        }
+        if (ok) out.push_back(s);
+    } while (std::next_permutation(s.begin(), s.begin() + p.k));
+    return out;
+}
+
+// Sets D.sym_mult and the `gt` masks; drops a reuse whose source was trimmed
+// by a bound the reusing descriptor does not have.
+void apply_symmetry(const Pat& p, PlanDesc& D) {
+    const int nc = (int)D.e + (D.t == 1 ? 1 : 0);  // conditioned positions in level order
+    uint32_t cmask = 0;
+    int pos_of[kMaxK];
+    for (int i = 0; i < kMaxK; i++) pos_of[i] = -1;
+    for (int i = 0; i < nc; i++) {
+        cmask |= 1u << D.order[i];
+        pos_of[D.order[i]] = i;
+    }
+    // H restricted to the conditioned vertices: distinct restrictions of the
+    // automorphisms that map that set onto itself
+    std::vector<Perm> grp;
+    for (const Perm& s : automorphisms(p)) {
+        uint32_t img = 0;
+        for (int v = 0; v < p.k; v++)
+            if (cmask & (1u << v)) img |= 1u << s[v];
+        if (img != cmask) continue;
+        Perm r{};
+        for (int v = 0; v < p.k; v++) r[v] = (cmask & (1u << v)) ? s[v] : (uint8_t)v;
+        if (std::find(grp.begin(), grp.end(), r) == grp.end()) grp.push_back(r);
+    }
+    D.sym_mult = (uint32_t)grp.size();
+    uint8_t gt[kMaxK + 1] = {0};  // by position
+    for (int i = 0; i < nc && grp.size() > 1; i++) {
+        const int v = D.order[i];
+        uint32_t orbit = 0;
+        for (const Perm& s : grp) orbit |= 1u << s[v];
+        orbit &= ~(1u << v);
+        // every vertex of the orbit comes later: the earlier ones are fixed
+        for (int u = 0; u < p.k; u++)
+            if (orbit & (1u << u)) gt[pos_of[u]] |= (uint8_t)(1u << i);
+        std::vector<Perm> stab;
+        for (const Perm& s : grp)
+            if (s[v] == v) stab.push_back(s);
+        grp.swap(stab);
+    }
+    for (uint32_t l = 1; l < D.e; l++) D.lvl[l].gt = gt[l];
+    if (D.t == 1) {
+        // one leaf: its signature and the one mask that measures its set
+        D.sig[0].gt = gt[D.e];
+        for (uint32_t i = 0; i < D.n_masks; i++) D.mdesc[i].gt = gt[D.e];
+    }
+    auto fix_reuse = [&](LevelDesc& L) {
+        if (L.reuse == kNoReuse) return;
+        if (D.lvl[L.reuse].gt & ~L.gt) {
+            L.reuse = kNoReuse;
+            L.extra = 0;
+        }
+    };
+    for (uint32_t l = 2; l < D.e; l++) fix_reuse(D.lvl[l]);
+    for (uint32_t g = 0; g < D.n_sig; g++) fix_reuse(D.sig[g]);
+    for (uint32_t i = 0; i < D.n_masks; i++) fix_reuse(D.mdesc[i]);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -456,9 +538,9 @@ std::string plan_json(const Pat& p, const PlanDesc& D, const CoverReport& cr, bo
             std::snprintf(buf, sizeof buf, "%s[%d,%d]", c ? "," : "", L.cons_lvl[c], L.cons_dir[c]);
             o += buf;
         }
-        std::snprintf(buf, sizeof buf, "],\"reuse\":%d,\"extra\":%u,\"inj\":%u,\"dmin\":[%u,%u]}",
+        std::snprintf(buf, sizeof buf, "],\"reuse\":%d,\"extra\":%u,\"inj\":%u,\"dmin\":[%u,%u],\"gt\":%u}",
                       L.reuse == kNoReuse ? -1 : (int)L.reuse, (unsigned)L.extra, (unsigned)L.inj,
-                      L.dmin_out, L.dmin_in);
+                      L.dmin_out, L.dmin_in, (unsigned)L.gt);
         o += buf;
         return o;
     };
@@ -475,8 +557,8 @@ std::string plan_json(const Pat& p, const PlanDesc& D, const CoverReport& cr, bo
         o += buf;
         s += o;
     }
-    std::snprintf(buf, sizeof buf, "],\"t\":%u,\"linear\":%u,\"seg_src\":%u,\"terms\":[", D.t, D.linear,
-                  D.seg_src);
+    std::snprintf(buf, sizeof buf, "],\"t\":%u,\"linear\":%u,\"seg_src\":%u,\"sym_mult\":%u,\"terms\":[", D.t,
+                  D.linear, D.seg_src, D.sym_mult ? D.sym_mult : 1u);
     s += buf;
     for (uint32_t i = 0; i < D.n_terms; i++) {
         std::snprintf(buf, sizeof buf, "%s{\"coef\":%d,\"masks\":[", i ? "," : "", D.terms[i].coef);
@@ -691,6 +773,8 @@ int build_plan(uint32_t k, uint32_t n_arcs, const uint8_t* arcs, uint32_t flags,
             D.mask_id[D.n_masks++] = (uint8_t)M;
         }
     }
+    D.sym_mult = 1;
+    if (flags & 0x4u) apply_symmetry(p, D);
     // packed constraint fields read by the kernel
     auto pack = [](LevelDesc& L) {
         L.dir_mask = 0;

@@ -154,6 +154,12 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
         for (uint32_t i = 0; i < D.n_masks; i++) L.maxc = std::max<uint32_t>(L.maxc, D.mdesc[i].n_cons);
         if (!D.linear) L.nonlinear = true;
         if (D.e >= 2) splittable++;
+        // a symmetry-broken plan counts one embedding per orbit: neither the
+        // embeddings of a root subset nor a listing can be read from it
+        if (D.sym_mult > 1 && o && o->roots_dev)
+            return fail(XM_ERR_INVALID, "root subsets need plans without XM_PLAN_SYMMETRY");
+        if (D.sym_mult > 1 && full_opts && o->list_dev)
+            return fail(XM_ERR_INVALID, "listing needs a plan without XM_PLAN_SYMMETRY");
     }
     L.merge_min = (o && o->merge_min) ? o->merge_min : xm::kMergeMin;
     L.lds_words = xm::lds_words_for(L.e_max, L.maxc, L.nonlinear, L.merge_min != 0xFFFFFFFFu);
@@ -699,7 +705,7 @@ int xm_plan(uint32_t k, uint32_t n_arcs, const uint8_t* arcs, uint32_t flags, co
             xm_plan_t** out) {
     if (!out) return fail(XM_ERR_INVALID, "out is NULL");
     *out = nullptr;
-    if (flags & ~(0x3u | 0xF00u)) return fail(XM_ERR_INVALID, "unknown plan flag");
+    if (flags & ~(0x7u | 0xF00u)) return fail(XM_ERR_INVALID, "unknown plan flag");
     xm_plan_t* p = new (std::nothrow) xm_plan_s;
     if (!p) return fail(XM_ERR_OOM, "host allocation");
     std::string err;

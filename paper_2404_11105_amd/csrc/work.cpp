@@ -29,7 +29,7 @@ struct Walker {
     uint64_t budget = 0;
     uint64_t reported = 0;
     bool stop = false;
-    uint32_t phi[kMaxK];
+    uint32_t phi[kMaxK] = {0};
     std::vector<uint32_t> cand[kMaxK];
 
     Walker(const HostCsr& g, const PlanDesc& p) : G(g), P(p) {}
@@ -44,9 +44,35 @@ struct Walker {
         return std::binary_search(a, a + len, x);
     }
 
+    // Largest bound image among the levels in D.gt (symmetry breaking).
+    uint32_t lower_bound_of(const LevelDesc& D) const {
+        uint32_t lb = 0;
+        for (uint32_t l = 0; l < kMaxK; l++)
+            if ((D.gt >> l) & 1u) lb = std::max(lb, phi[l]);
+        return lb;
+    }
+
+    // Drop the elements <= lb from a sorted list.
+    static void suffix(const uint32_t*& a, uint32_t& len, uint32_t lb) {
+        const uint32_t skip = (uint32_t)(std::upper_bound(a, a + len, lb) - a);
+        a += skip;
+        len -= skip;
+    }
+
     // Base and probe lists of level desc D at depth lv (levels < lv bound).
+    // With a symmetry bound, only the parts above it are counted: candidates
+    // are the base's suffix, and a merge would start each probe list there.
     void lists(const LevelDesc& D, bool& from_level, const uint32_t*& base, uint32_t& blen,
                const uint32_t* probe[kMaxCons], uint32_t plen[kMaxCons], int& np) {
+        lists_all(D, from_level, base, blen, probe, plen, np);
+        if (!D.gt) return;
+        const uint32_t lb = lower_bound_of(D);
+        suffix(base, blen, lb);
+        for (int i = 0; i < np; i++) suffix(probe[i], plen[i], lb);
+    }
+
+    void lists_all(const LevelDesc& D, bool& from_level, const uint32_t*& base, uint32_t& blen,
+                   const uint32_t* probe[kMaxCons], uint32_t plen[kMaxCons], int& np) {
         np = 0;
         from_level = D.reuse != kNoReuse;
         if (from_level) {
@@ -81,6 +107,7 @@ struct Walker {
             const uint32_t* a;
             uint32_t l;
             list(phi[S0.cons_lvl[0]], S0.cons_dir[0], a, l);
+            if (S0.gt) suffix(a, l, lower_bound_of(S0));
             w.elements += l;
             w.fetches += 1;
             return;

@@ -41,3 +41,27 @@ CASES = {
                           roots=np.array([0, 1, 2, 5, 17, 100, 1000, 2047], dtype=np.uint32),
                           root_vertex=[0, 0, 2, 1]),
 }
+
+
+def symmetric_patterns():
+    """Patterns with non-trivial automorphism groups: named ones, a few built
+    by hand and the first random draws (k = 3..6) that have any."""
+    P = xmgen.Pattern
+    out = [xmgen.named(n) for n in ["c3", "c4", "bifan", "outstar3", "instar3", "mixed_star", "pair2"]]
+    out += [P(3, ((0, 1), (1, 0), (1, 2), (2, 1), (0, 2), (2, 0)), "bitri"),
+            P(4, tuple((a, b) for a in range(4) for b in range(4) if a != b), "k4"),
+            P(5, ((0, 1), (1, 2), (2, 3), (3, 4), (4, 0)), "c5"),
+            P(4, ((0, 1), (1, 0), (1, 2), (2, 1), (2, 3), (3, 2), (3, 0), (0, 3)), "bic4"),
+            P(5, ((0, 2), (0, 3), (0, 4), (1, 2), (1, 3), (1, 4)), "k23"),
+            P(5, ((0, 1), (1, 2), (0, 2), (0, 3), (3, 4), (0, 4)), "two_ffl")]
+    for k in range(3, 7):
+        got = 0
+        for s in range(400):
+            pat = xmgen.random_pattern(k, 9000 + 100 * k + s)
+            if pat.automorphisms() > 1:
+                out.append(pat)
+                got += 1
+                if got == 2:
+                    break
+    return out
+

@@ -90,6 +90,16 @@ class Model:
                 meta["off"] += lo
                 ln = hi - lo
         meta["len"] = ln
+        if D.get("gt", 0):
+            # symmetry breaking: the sorted base's suffix above the bound
+            lb = max(bound[l] for l in range(lv) if (D["gt"] >> l) & 1)
+            skip = 0
+            while skip < ln and self.base_elem(meta, skip, D["reuse"]) <= lb:
+                skip += 1
+            for i in range(skip + 1, ln):
+                assert self.base_elem(meta, i - 1, D["reuse"]) < self.base_elem(meta, i, D["reuse"]), "unsorted base"
+            meta["off"] += skip
+            meta["len"] = ln - skip
         return meta
 
     def base_elem(self, meta, local, reuse):
@@ -200,8 +210,13 @@ class Model:
                     j, d = S0["cons"][0]
                     lo, hi = self._rng(bound[j], d)
                     L = self.sets[d][bound[j]]
+                    lb = -1
+                    if S0.get("gt", 0):
+                        lb = max(bound[l] for l in range(lv + 1) if (S0["gt"] >> l) & 1)
+                        while lo < hi and self.adj(d)[lo] <= lb:
+                            lo += 1
                     self.total += (hi - lo) - sum(1 for b in range(lv + 1)
-                                                  if (S0["inj"] >> b) & 1 and bound[b] in L)
+                                                  if (S0["inj"] >> b) & 1 and bound[b] in L and bound[b] > lb)
                     continue
                 # several signatures: h[M] = |intersection of the sets in M| for
                 # every mask the terms use, then the inclusion-exclusion terms
@@ -290,4 +305,4 @@ class Model:
                 n0 += 1
             if n0:
                 self.explore(n0)
-        return self.total
+        return self.total * P.get("sym_mult", 1)

@@ -29,9 +29,9 @@ def xa():
     return xa
 
 
-def run(xa, g, pats, reduced=True, G=None, **opts):
+def run(xa, g, pats, reduced=True, G=None, symmetry=False, **opts):
     G = G or xa.Graph(g)
-    plans = [xa.Plan(p, reduced=reduced, graph=G) for p in pats]
+    plans = [xa.Plan(p, reduced=reduced, graph=G, symmetry=symmetry) for p in pats]
     c = xa.Counter(G, plans, **opts)
     c.run()
     counts, status = c.results()
@@ -192,6 +192,9 @@ def test_config2_full_size(xa):
     want = [int(gold[n]) for n in names]
     assert run(xa, g, pats, G=G, reduced=True) == want
     assert run(xa, g, pats, G=G, reduced=False) == want
+    banner("  symmetry-broken plans")
+    assert run(xa, g, pats, G=G, reduced=True, symmetry=True) == want
+    assert run(xa, g, pats, G=G, reduced=False, symmetry=True) == want
 
 
 
@@ -253,3 +256,58 @@ def test_listing_rejects_multi_leaf_plans(xa):
     G = xa.Graph(g)
     with pytest.raises(Exception):
         xa.list_embeddings(G, xmgen.named("outstar3"), cap=100, reduced=True)
+
+
+@pytest.mark.parametrize("tune", [dict(), dict(chunk=1, split=64, cap=64),
+                                  dict(chunk=64, split=64, cap=128, split_work=4096)])
+def test_symmetry_broken_plans_vs_oracle(xa, tune):
+    """Plans that count one embedding per automorphism orbit and scale by the
+    orbit size give the oracle's labelled counts: all patterns in one batched
+    launch (mixed multipliers), reduced and unreduced, with hub splits and
+    partial windows forced by the small tunings."""
+    from tests.cases import symmetric_patterns
+    pats = symmetric_patterns()
+    for g in (xmgen.rmat(9, seed=3), xmgen.uniform_digraph(300, 2400, 5)):
+        banner(f"symmetry-broken plans on {g.name}, {len(pats)} patterns, tuning {tune}")
+        G = xa.Graph(g)
+        want = [oracle.count(g, p, threads=8, mode="B") for p in pats]
+        for reduced in (True, False):
+            assert run(xa, g, pats, G=G, reduced=reduced, symmetry=True, **tune) == want, reduced
+
+
+def test_symmetry_closed_forms(xa):
+    """Complete digraph: n!/(n-k)! for every pattern.  Out-star hub: the
+    falling factorial above 2^64 with the reduced plan (its leaf group holds
+    every leaf, so the multiplier is 1: an unreduced plan there would
+    enumerate ~10^18 prefixes even with symmetry breaking)."""
+    banner("symmetry-broken plans: complete digraph 9 and the out-star hub")
+    g = xmgen.complete_digraph(9)
+    pats = [xmgen.named(n) for n in NAMED] + [xmgen.random_pattern(k, 77 + k) for k in range(3, 8)]
+    want = [pins.complete_count(9, p.k) for p in pats]
+    assert run(xa, g, pats, symmetry=True) == want
+    assert run(xa, g, pats, reduced=False, symmetry=True) == want
+    D = 100000
+    g = xmgen.star_hub(D)
+    for name, k in (("outstar5", 5), ("outstar3", 3)):
+        assert run(xa, g, [xmgen.named(name)], symmetry=True) == [pins.falling(D, k)]
+
+
+def test_symmetry_rejects_root_subsets_and_listing(xa):
+    banner("symmetry-broken plans refuse root subsets and listing")
+    g = xmgen.uniform_digraph(60, 400, 12)
+    G = xa.Graph(g)
+    p = xa.Plan(xmgen.named("c4"), graph=G, symmetry=True)
+    assert p.describe()["sym_mult"] == 4
+    with pytest.raises(Exception):
+        c = xa.Counter(G, [p], roots=np.arange(10, dtype=np.uint32))
+        c.run()
+    with pytest.raises(Exception):
+        c = xa.Counter(G, [p], list_cap=100)
+        c.run()
+    # a pattern without symmetry keeps a plain plan: subsets still work
+    q = xa.Plan(xmgen.named("ffl"), graph=G, symmetry=True)
+    assert q.describe()["sym_mult"] == 1
+    c = xa.Counter(G, [q], roots=np.arange(g.n, dtype=np.uint32))
+    c.run()
+    got, st = c.results()
+    assert got == [oracle.count(g, xmgen.named("ffl"))] and st == [0]

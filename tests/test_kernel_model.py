@@ -9,6 +9,7 @@ import pytest
 import oracle
 import xmgen
 from paper_2404_11105_amd import describe_plan
+from tests.cases import symmetric_patterns
 from tests.kernel_model import Model
 
 TUNINGS = [dict(chunk=1, split=64, cap=64), dict(chunk=64, split=64, cap=128, split_work=4096),
@@ -39,3 +40,35 @@ def test_model_random_patterns_small_cap():
             for reduced in (True, False):
                 m = Model(describe_plan(pat, reduced), g, chunk=3, split=64, cap=64)
                 assert m.run() == want, (k, s, reduced)
+
+
+def test_symmetry_multiplier_is_the_orbit_size():
+    """With one counted leaf every vertex is conditioned, so the multiplier is
+    |Aut(P)| (counted here by brute force); in general it divides it."""
+    for pat in symmetric_patterns():
+        aut = pat.automorphisms()
+        for reduced in (True, False):
+            d = describe_plan(pat, reduced, symmetry=True)
+            assert aut % d["sym_mult"] == 0, (pat.name, reduced)
+            if d["t"] == 1:
+                assert d["sym_mult"] == aut, (pat.name, reduced)
+            # a bound only ever refers to earlier levels
+            for i, L in enumerate(d["levels"], start=1):
+                assert L["gt"] < (1 << i)
+        assert describe_plan(pat, True)["sym_mult"] == 1  # off unless asked for
+
+
+@pytest.mark.parametrize("tune", TUNINGS[:2], ids=lambda t: f"c{t['chunk']}s{t['split']}k{t['cap']}")
+def test_model_symmetry_broken_plans_match_oracle(tune):
+    """Counting one embedding per orbit and scaling gives the oracle's
+    labelled count, with hub splits and partial windows forced."""
+    hub = xmgen.rmat(7, seed=7)  # lists longer than a split: hub roots are split
+    small = xmgen.uniform_digraph(40, 420, 11)
+    for g in (hub, small):
+        for pat in symmetric_patterns():
+            if g is hub and (pat.k > 4 or pat.name == "mixed_star") and pat.name not in ("k23", "c5"):
+                continue  # the pure-Python model is slow on these there
+            want = oracle.count(g, pat)
+            for reduced in (True, False):
+                m = Model(describe_plan(pat, reduced, symmetry=True), g, **tune, max_windows=400000)
+                assert m.run() == want, (pat.name, reduced)
