@@ -28,6 +28,7 @@ XM_VALIDATE = 0x4
 XM_PLAN_REDUCED = 0x1
 XM_PLAN_UNREDUCED = 0x2
 XM_PLAN_SYMMETRY = 0x4
+XM_PLAN_SYM_BELOW = 0x8
 
 
 def XM_PLAN_ROOT(v: int) -> int:

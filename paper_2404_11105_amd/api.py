@@ -7,6 +7,7 @@
 from __future__ import annotations
 
 import ctypes
+import os
 import json
 
 import numpy as np
@@ -52,8 +53,10 @@ class Graph:
         if all(isinstance(x, torch.Tensor) for x in arrays):
             # already device-resident int32 tensors holding uint32 values
             self.tensors = [x.to(self.device).contiguous() for x in arrays]
+            self.host = None
         else:
             self.tensors = [_u32_tensor(x, self.device) for x in arrays]
+            self.host = digraph  # host CSR, kept for planning estimates
         self.nbytes = sum(t.numel() * 4 for t in self.tensors)
         h = ctypes.c_void_p()
         flags = _lib.XM_MEM_DEVICE | (_lib.XM_VALIDATE if validate else 0)
@@ -107,20 +110,29 @@ class Graph:
 class Plan:
     """A counting plan for one pattern (reduced or unreduced).
 
-    symmetry=True counts one embedding per orbit of the pattern's
-    automorphisms on the enumerated vertices and scales the total by the orbit
-    size (same counts, less work); such a plan cannot count a root subset or
-    list embeddings."""
+    symmetry counts one embedding per orbit of the pattern's automorphisms on
+    the enumerated vertices and scales the total by the orbit size (same
+    counts, less work); such a plan cannot count a root subset or list
+    embeddings.  "above" keeps, per orbit, the embedding whose first
+    conditioned vertex has the smallest image; "below" the largest; True picks
+    the one with less estimated work on `graph` (a sampled host walk), or
+    "above" without a host copy of the graph."""
 
     def __init__(self, pattern, reduced: bool = True, graph: Graph | None = None,
-                 root_vertex: int | None = None, symmetry: bool = False):
+                 root_vertex: int | None = None, symmetry=False):
         self.pattern = pattern
         self.reduced = reduced
+        if symmetry is True:
+            symmetry = _choose_direction(pattern, reduced, graph, root_vertex)
+        if symmetry not in (False, "above", "below"):
+            raise ValueError("symmetry must be False, True, 'above' or 'below'")
         self.symmetry = symmetry
         arcs = (ctypes.c_uint8 * max(1, 2 * len(pattern.arcs)))(*pattern.arcs_u8())
         flags = _lib.XM_PLAN_REDUCED if reduced else _lib.XM_PLAN_UNREDUCED
         if symmetry:
             flags |= _lib.XM_PLAN_SYMMETRY
+        if symmetry == "below":
+            flags |= _lib.XM_PLAN_SYM_BELOW
         if root_vertex is not None:
             flags |= _lib.XM_PLAN_ROOT(root_vertex)
         h = ctypes.c_void_p()
@@ -155,8 +167,46 @@ def plan_json(plan: Plan) -> str:
     return buf.value.decode()
 
 
-def describe_plan(pattern, reduced: bool = True, symmetry: bool = False) -> dict:
+def describe_plan(pattern, reduced: bool = True, symmetry=False) -> dict:
     return Plan(pattern, reduced, symmetry=symmetry).describe()
+
+
+SYM_FETCH_COST = 64      # one list fetch weighs as much as this many elements
+SYM_SAMPLE_HUBS = 64     # longest-listed nodes always in the sample
+SYM_SAMPLE_REST = 4096   # other nodes, strided
+SYM_WALK_CAP = 200_000_000  # partial matches per estimate
+
+
+def _choose_direction(pattern, reduced, graph, root_vertex):
+    """The symmetry direction with the smaller estimated work: the host walk
+    (elements + SYM_FETCH_COST x list fetches) over the hub roots and a
+    strided sample of the others, scaled to all roots.  Patterns without
+    symmetry, graphs without a host copy and walks past the cap keep
+    "above"."""
+    if graph is None or getattr(graph, "host", None) is None:
+        return "above"
+    g = graph.host
+    cand = {d: Plan(pattern, reduced, root_vertex=root_vertex, symmetry=d) for d in ("above", "below")}
+    if cand["above"].describe()["sym_mult"] == 1:
+        return "above"
+    deg = np.diff(np.asarray(g.out_off, dtype=np.int64)) + np.diff(np.asarray(g.in_off, dtype=np.int64))
+    n = deg.size
+    hubs = np.argsort(-deg, kind="stable")[:SYM_SAMPLE_HUBS]
+    rest = np.setdiff1d(np.arange(0, n, max(1, n // SYM_SAMPLE_REST)), hubs)
+    w_rest = (n - hubs.size) / max(1, rest.size)
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    cost = {}
+    for d, p in cand.items():
+        tot = 0.0
+        for roots, w in ((hubs, 1.0), (rest, w_rest)):
+            if roots.size == 0:
+                continue
+            r = plan_work(g, p, roots=roots.astype(np.uint32), threads=threads, max_partial=SYM_WALK_CAP)
+            if r["exceeded"]:
+                return "above"
+            tot += w * (r["elements"] + SYM_FETCH_COST * r["fetches"])
+        cost[d] = tot
+    return "below" if cost["below"] < cost["above"] else "above"
 
 
 def make_opts(chunk=0, split=0, cap=0, waves_per_cu=0, roots=None, cancel=None, events=None,

@@ -123,7 +123,7 @@ __device__ __forceinline__ const uint32_t* safe_ptr(const DevGraph& g) {
 
 // Per-level constraint fields, loaded once into scalar registers.
 struct LK {
-    uint32_t n_cons, reuse, inj, deg_check, extra, dirm, dmin_out, dmin_in, gt;
+    uint32_t n_cons, reuse, inj, deg_check, extra, dirm, dmin_out, dmin_in, gt, lt;
     uint64_t lvlb;
     __device__ __forceinline__ uint32_t lvl(uint32_t c) const { return (uint32_t)(lvlb >> (3 * c)) & 7u; }
     __device__ __forceinline__ uint32_t dir(uint32_t c) const { return (dirm >> c) & 1u; }
@@ -144,6 +144,7 @@ __device__ __forceinline__ LK load_lk(const LevelDesc& D, const KArgs& a) {
     k.dmin_out = uni(D.dmin_out);
     k.dmin_in = uni(D.dmin_in);
     k.gt = uni(D.gt);
+    k.lt = uni(D.lt);
     k.lvlb = ((uint64_t)uni((uint32_t)(D.lvl_bits >> 32)) << 32) | uni((uint32_t)D.lvl_bits);
     return k;
 }
@@ -240,18 +241,6 @@ __device__ __forceinline__ uint32_t level1_len(const DevGraph& g, const PlanDesc
     return best;
 }
 
-// Largest bound image among the levels in gt (levels < lv) of this lane's
-// partial match.
-__device__ __forceinline__ uint32_t lower_bound_of(const Lds& s, uint32_t gt, uint32_t lv, uint32_t lane) {
-    uint32_t lb = 0;
-    for (uint32_t l = 0; l < lv; l++)
-        if ((gt >> l) & 1u) {
-            const uint32_t b = s.bound[l * 64 + lane];
-            lb = b > lb ? b : lb;
-        }
-    return lb;
-}
-
 // Number of elements <= x in the sorted list a[0, n).
 __device__ __forceinline__ uint32_t count_le(const uint32_t* __restrict__ a, uint32_t n, uint32_t x) {
     uint32_t lo = 0;
@@ -265,6 +254,27 @@ __device__ __forceinline__ uint32_t count_le(const uint32_t* __restrict__ a, uin
         }
     }
     return lo;
+}
+
+// Symmetry breaking: the part of the sorted list a[0, len) that lies above
+// the largest (lt = 0) or below the smallest (lt = 1) bound image among the
+// levels in gt (levels < lv) of this lane's partial match.
+__device__ __forceinline__ void sym_trim(const Lds& s, uint32_t gt, uint32_t lt, uint32_t lv, uint32_t lane,
+                                         const uint32_t*& a, uint32_t& len) {
+    uint32_t lo = 0xFFFFFFFFu, hi = 0;
+    for (uint32_t l = 0; l < lv; l++)
+        if ((gt >> l) & 1u) {
+            const uint32_t b = s.bound[l * 64 + lane];
+            lo = b < lo ? b : lo;
+            hi = b > hi ? b : hi;
+        }
+    if (lt) {
+        len = lo ? count_le(a, len, lo - 1u) : 0u;
+    } else {
+        const uint32_t skip = count_le(a, len, hi);
+        a += skip;
+        len -= skip;
+    }
 }
 
 // Phase A of a level: lane = one partial match (parent) of the window.  Walks
@@ -354,14 +364,8 @@ __device__ uint32_t phase_a(Ctx& C, const LK& D, uint32_t lv, uint32_t p, bool p
         }
     }
     for (; k < D.n_cons; k++) put(k, safe_ptr(g), kSkip);
-    if (D.gt) {
-        // symmetry breaking: only candidates above the largest image of the
-        // levels in gt; the base is sorted, so they are a suffix of it
-        const uint32_t lb = lower_bound_of(C.s, D.gt, lv, lane);
-        const uint32_t skip = count_le(base, len, lb);
-        base += skip;
-        len -= skip;
-    }
+    // symmetry breaking: the base is sorted, so its candidates are a range
+    if (D.gt) sym_trim(C.s, D.gt, D.lt, lv, lane, base, len);
     const uint64_t bv = reinterpret_cast<uint64_t>(base);
     C.s.base_lo[lane] = (uint32_t)bv;
     C.s.base_hi[lane] = (uint32_t)(bv >> 32);
@@ -793,12 +797,7 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
                 uint32_t o = off[nd];
                 uint32_t l = off[nd + 1] - o;
                 const uint32_t* L = adj_of(g, S0.dir(0)) + o;
-                if (S0.gt) {
-                    // symmetry breaking: the suffix above the bound
-                    const uint32_t skip = count_le(L, l, lower_bound_of(C.s, S0.gt, nb, lane));
-                    L += skip;
-                    l -= skip;
-                }
+                if (S0.gt) sym_trim(C.s, S0.gt, S0.lt, nb, lane, L, l);
                 v = l;
                 for (uint32_t b = 0; b < nb; b++)
                     if (((S0.inj >> b) & 1u) && contains(L, l, C.s.bound[b * 64 + lane])) v -= 1;

@@ -33,7 +33,9 @@
 // phi(v_j) < phi(v_i) (j earlier than i) that exactly one partial match of
 // every H-orbit meets; the plan counts those and scales by |H| restricted to
 // the conditioned vertices (sym_mult).  Only a lower bound arises per level:
-// the largest image among the levels in `gt`.
+// the largest image among the levels in `gt` (or, with the conditions
+// reversed, phi(v_i) < phi(v_j), an upper bound: the smallest image).  Both
+// directions are exact; which one enumerates less depends on the graph.
 #pragma once
 #include <stdint.h>
 
@@ -59,8 +61,9 @@ struct LevelDesc {
     uint8_t cons_dir[kMaxCons];   // 0: out(phi(v_j)), 1: in(phi(v_j))
     uint32_t dmin_out, dmin_in;
     uint64_t lvl_bits;            // cons_lvl[c] at bits [3c, 3c+3) (packed copy)
-    uint8_t gt;                   // bit j: keep only candidates x > phi(v_j) (symmetry breaking)
-    uint8_t pad[7];
+    uint8_t gt;                   // bit j: phi(v_j) bounds the candidates (symmetry breaking)
+    uint8_t lt;                   // 0: keep x > every bound; 1: keep x < every bound
+    uint8_t pad[6];
 };
 
 struct Term {

@@ -454,7 +454,7 @@ std::vector<Perm> automorphisms(const Pat& p) {
 
 // Sets D.sym_mult and the `gt` masks; drops a reuse whose source was trimmed
 // by a bound the reusing descriptor does not have.
-void apply_symmetry(const Pat& p, PlanDesc& D) {
+void apply_symmetry(const Pat& p, PlanDesc& D, bool below) {
     const int nc = (int)D.e + (D.t == 1 ? 1 : 0);  // conditioned positions in level order
     uint32_t cmask = 0;
     int pos_of[kMaxK];
@@ -490,6 +490,10 @@ void apply_symmetry(const Pat& p, PlanDesc& D) {
             if (s[v] == v) stab.push_back(s);
         grp.swap(stab);
     }
+    const uint8_t lt = below ? 1 : 0;
+    for (uint32_t l = 1; l < D.e; l++) D.lvl[l].lt = lt;
+    for (uint32_t g = 0; g < D.n_sig; g++) D.sig[g].lt = lt;
+    for (uint32_t i = 0; i < D.n_masks; i++) D.mdesc[i].lt = lt;
     for (uint32_t l = 1; l < D.e; l++) D.lvl[l].gt = gt[l];
     if (D.t == 1) {
         // one leaf: its signature and the one mask that measures its set
@@ -538,9 +542,9 @@ std::string plan_json(const Pat& p, const PlanDesc& D, const CoverReport& cr, bo
             std::snprintf(buf, sizeof buf, "%s[%d,%d]", c ? "," : "", L.cons_lvl[c], L.cons_dir[c]);
             o += buf;
         }
-        std::snprintf(buf, sizeof buf, "],\"reuse\":%d,\"extra\":%u,\"inj\":%u,\"dmin\":[%u,%u],\"gt\":%u}",
+        std::snprintf(buf, sizeof buf, "],\"reuse\":%d,\"extra\":%u,\"inj\":%u,\"dmin\":[%u,%u],\"gt\":%u,\"lt\":%u}",
                       L.reuse == kNoReuse ? -1 : (int)L.reuse, (unsigned)L.extra, (unsigned)L.inj,
-                      L.dmin_out, L.dmin_in, (unsigned)L.gt);
+                      L.dmin_out, L.dmin_in, (unsigned)L.gt, (unsigned)L.lt);
         o += buf;
         return o;
     };
@@ -774,7 +778,7 @@ int build_plan(uint32_t k, uint32_t n_arcs, const uint8_t* arcs, uint32_t flags,
         }
     }
     D.sym_mult = 1;
-    if (flags & 0x4u) apply_symmetry(p, D);
+    if (flags & 0x4u) apply_symmetry(p, D, (flags & 0x8u) != 0);
     // packed constraint fields read by the kernel
     auto pack = [](LevelDesc& L) {
         L.dir_mask = 0;

@@ -705,7 +705,7 @@ int xm_plan(uint32_t k, uint32_t n_arcs, const uint8_t* arcs, uint32_t flags, co
             xm_plan_t** out) {
     if (!out) return fail(XM_ERR_INVALID, "out is NULL");
     *out = nullptr;
-    if (flags & ~(0x7u | 0xF00u)) return fail(XM_ERR_INVALID, "unknown plan flag");
+    if (flags & ~(0xFu | 0xF00u)) return fail(XM_ERR_INVALID, "unknown plan flag");
     xm_plan_t* p = new (std::nothrow) xm_plan_s;
     if (!p) return fail(XM_ERR_OOM, "host allocation");
     std::string err;

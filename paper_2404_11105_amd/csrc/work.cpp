@@ -44,31 +44,34 @@ struct Walker {
         return std::binary_search(a, a + len, x);
     }
 
-    // Largest bound image among the levels in D.gt (symmetry breaking).
-    uint32_t lower_bound_of(const LevelDesc& D) const {
-        uint32_t lb = 0;
+    // Symmetry breaking: keep the part of a sorted list above the largest
+    // (D.lt = 0) or below the smallest (D.lt = 1) image of the levels in D.gt.
+    void trim(const LevelDesc& D, const uint32_t*& a, uint32_t& len) const {
+        uint32_t lo = 0xFFFFFFFFu, hi = 0;
         for (uint32_t l = 0; l < kMaxK; l++)
-            if ((D.gt >> l) & 1u) lb = std::max(lb, phi[l]);
-        return lb;
-    }
-
-    // Drop the elements <= lb from a sorted list.
-    static void suffix(const uint32_t*& a, uint32_t& len, uint32_t lb) {
-        const uint32_t skip = (uint32_t)(std::upper_bound(a, a + len, lb) - a);
-        a += skip;
-        len -= skip;
+            if ((D.gt >> l) & 1u) {
+                lo = std::min(lo, phi[l]);
+                hi = std::max(hi, phi[l]);
+            }
+        if (D.lt) {
+            len = (uint32_t)(std::lower_bound(a, a + len, lo) - a);
+        } else {
+            const uint32_t skip = (uint32_t)(std::upper_bound(a, a + len, hi) - a);
+            a += skip;
+            len -= skip;
+        }
     }
 
     // Base and probe lists of level desc D at depth lv (levels < lv bound).
-    // With a symmetry bound, only the parts above it are counted: candidates
-    // are the base's suffix, and a merge would start each probe list there.
+    // With a symmetry bound, only the parts on its side are counted:
+    // candidates are a range of the base, and a merge would read only that
+    // range of each probe list.
     void lists(const LevelDesc& D, bool& from_level, const uint32_t*& base, uint32_t& blen,
                const uint32_t* probe[kMaxCons], uint32_t plen[kMaxCons], int& np) {
         lists_all(D, from_level, base, blen, probe, plen, np);
         if (!D.gt) return;
-        const uint32_t lb = lower_bound_of(D);
-        suffix(base, blen, lb);
-        for (int i = 0; i < np; i++) suffix(probe[i], plen[i], lb);
+        trim(D, base, blen);
+        for (int i = 0; i < np; i++) trim(D, probe[i], plen[i]);
     }
 
     void lists_all(const LevelDesc& D, bool& from_level, const uint32_t*& base, uint32_t& blen,
@@ -107,7 +110,7 @@ struct Walker {
             const uint32_t* a;
             uint32_t l;
             list(phi[S0.cons_lvl[0]], S0.cons_dir[0], a, l);
-            if (S0.gt) suffix(a, l, lower_bound_of(S0));
+            if (S0.gt) trim(S0, a, l);
             w.elements += l;
             w.fetches += 1;
             return;
@@ -210,6 +213,8 @@ bool plan_work(const HostCsr& g, const PlanDesc& p, const uint32_t* roots, uint3
     uint64_t total = roots ? n_roots : g.n;
     threads = std::max(1u, threads);
     std::vector<WorkOut> parts(threads);
+    // small root lists (a sample of hubs) spread one root at a time
+    const uint64_t step = std::max<uint64_t>(1, std::min<uint64_t>(64, total / (16ull * threads)));
     std::vector<std::thread> ts;
     for (unsigned t = 0; t < threads; t++) {
         ts.emplace_back([&, t]() {
@@ -217,9 +222,9 @@ bool plan_work(const HostCsr& g, const PlanDesc& p, const uint32_t* roots, uint3
             wk.shared_partial = &partial;
             wk.budget = max_partial;
             for (;;) {
-                uint64_t b = cursor.fetch_add(64);
+                uint64_t b = cursor.fetch_add(step);
                 if (b >= total || wk.stop || exceeded.load()) break;
-                uint64_t e = std::min<uint64_t>(total, b + 64);
+                uint64_t e = std::min<uint64_t>(total, b + step);
                 for (uint64_t i = b; i < e && !wk.stop; i++) {
                     uint32_t r = roots ? roots[i] : (uint32_t)i;
                     if (r < g.n) wk.root(r);

@@ -91,15 +91,16 @@ class Model:
                 ln = hi - lo
         meta["len"] = ln
         if D.get("gt", 0):
-            # symmetry breaking: the sorted base's suffix above the bound
-            lb = max(bound[l] for l in range(lv) if (D["gt"] >> l) & 1)
-            skip = 0
-            while skip < ln and self.base_elem(meta, skip, D["reuse"]) <= lb:
-                skip += 1
-            for i in range(skip + 1, ln):
-                assert self.base_elem(meta, i - 1, D["reuse"]) < self.base_elem(meta, i, D["reuse"]), "unsorted base"
-            meta["off"] += skip
-            meta["len"] = ln - skip
+            # symmetry breaking: the sorted base's range beyond the bounds
+            bs = [bound[l] for l in range(lv) if (D["gt"] >> l) & 1]
+            elems = [self.base_elem(meta, i, D["reuse"]) for i in range(ln)]
+            assert all(x < y for x, y in zip(elems, elems[1:])), "unsorted base"
+            if D["lt"]:
+                meta["len"] = sum(1 for x in elems if x < min(bs))
+            else:
+                skip = sum(1 for x in elems if x <= max(bs))
+                meta["off"] += skip
+                meta["len"] = ln - skip
         return meta
 
     def base_elem(self, meta, local, reuse):
@@ -210,13 +211,16 @@ class Model:
                     j, d = S0["cons"][0]
                     lo, hi = self._rng(bound[j], d)
                     L = self.sets[d][bound[j]]
-                    lb = -1
+                    keep = lambda x: True  # noqa: E731
                     if S0.get("gt", 0):
-                        lb = max(bound[l] for l in range(lv + 1) if (S0["gt"] >> l) & 1)
-                        while lo < hi and self.adj(d)[lo] <= lb:
-                            lo += 1
-                    self.total += (hi - lo) - sum(1 for b in range(lv + 1)
-                                                  if (S0["inj"] >> b) & 1 and bound[b] in L and bound[b] > lb)
+                        bs = [bound[l] for l in range(lv + 1) if (S0["gt"] >> l) & 1]
+                        if S0["lt"]:
+                            keep = lambda x: x < min(bs)  # noqa: E731
+                        else:
+                            keep = lambda x: x > max(bs)  # noqa: E731
+                    n_in = sum(1 for i in range(lo, hi) if keep(self.adj(d)[i]))
+                    self.total += n_in - sum(1 for b in range(lv + 1)
+                                             if (S0["inj"] >> b) & 1 and bound[b] in L and keep(bound[b]))
                     continue
                 # several signatures: h[M] = |intersection of the sets in M| for
                 # every mask the terms use, then the inclusion-exclusion terms

@@ -192,9 +192,10 @@ def test_config2_full_size(xa):
     want = [int(gold[n]) for n in names]
     assert run(xa, g, pats, G=G, reduced=True) == want
     assert run(xa, g, pats, G=G, reduced=False) == want
-    banner("  symmetry-broken plans")
-    assert run(xa, g, pats, G=G, reduced=True, symmetry=True) == want
-    assert run(xa, g, pats, G=G, reduced=False, symmetry=True) == want
+    for direction in ("above", "below"):
+        banner(f"  symmetry-broken plans, {direction}")
+        assert run(xa, g, pats, G=G, reduced=True, symmetry=direction) == want
+        assert run(xa, g, pats, G=G, reduced=False, symmetry=direction) == want
 
 
 
@@ -258,9 +259,10 @@ def test_listing_rejects_multi_leaf_plans(xa):
         xa.list_embeddings(G, xmgen.named("outstar3"), cap=100, reduced=True)
 
 
+@pytest.mark.parametrize("direction", ["above", "below"])
 @pytest.mark.parametrize("tune", [dict(), dict(chunk=1, split=64, cap=64),
                                   dict(chunk=64, split=64, cap=128, split_work=4096)])
-def test_symmetry_broken_plans_vs_oracle(xa, tune):
+def test_symmetry_broken_plans_vs_oracle(xa, tune, direction):
     """Plans that count one embedding per automorphism orbit and scale by the
     orbit size give the oracle's labelled counts: all patterns in one batched
     launch (mixed multipliers), reduced and unreduced, with hub splits and
@@ -268,11 +270,11 @@ def test_symmetry_broken_plans_vs_oracle(xa, tune):
     from tests.cases import symmetric_patterns
     pats = symmetric_patterns()
     for g in (xmgen.rmat(9, seed=3), xmgen.uniform_digraph(300, 2400, 5)):
-        banner(f"symmetry-broken plans on {g.name}, {len(pats)} patterns, tuning {tune}")
+        banner(f"symmetry-broken plans ({direction}) on {g.name}, {len(pats)} patterns, tuning {tune}")
         G = xa.Graph(g)
         want = [oracle.count(g, p, threads=8, mode="B") for p in pats]
         for reduced in (True, False):
-            assert run(xa, g, pats, G=G, reduced=reduced, symmetry=True, **tune) == want, reduced
+            assert run(xa, g, pats, G=G, reduced=reduced, symmetry=direction, **tune) == want, reduced
 
 
 def test_symmetry_closed_forms(xa):
@@ -284,8 +286,9 @@ def test_symmetry_closed_forms(xa):
     g = xmgen.complete_digraph(9)
     pats = [xmgen.named(n) for n in NAMED] + [xmgen.random_pattern(k, 77 + k) for k in range(3, 8)]
     want = [pins.complete_count(9, p.k) for p in pats]
-    assert run(xa, g, pats, symmetry=True) == want
-    assert run(xa, g, pats, reduced=False, symmetry=True) == want
+    for direction in ("above", "below"):
+        assert run(xa, g, pats, symmetry=direction) == want
+        assert run(xa, g, pats, reduced=False, symmetry=direction) == want
     D = 100000
     g = xmgen.star_hub(D)
     for name, k in (("outstar5", 5), ("outstar3", 3)):

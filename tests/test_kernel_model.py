@@ -50,6 +50,12 @@ def test_symmetry_multiplier_is_the_orbit_size():
         for reduced in (True, False):
             d = describe_plan(pat, reduced, symmetry=True)
             assert aut % d["sym_mult"] == 0, (pat.name, reduced)
+            # the reversed conditions: same orbits, same bound levels
+            e = describe_plan(pat, reduced, symmetry="below")
+            assert e["sym_mult"] == d["sym_mult"]
+            assert [L["gt"] for L in e["levels"]] == [L["gt"] for L in d["levels"]]
+            assert all(L["lt"] == 1 for L in e["levels"] + e["leaf_sigs"])
+            assert all(L["lt"] == 0 for L in d["levels"] + d["leaf_sigs"])
             if d["t"] == 1:
                 assert d["sym_mult"] == aut, (pat.name, reduced)
             # a bound only ever refers to earlier levels
@@ -58,8 +64,9 @@ def test_symmetry_multiplier_is_the_orbit_size():
         assert describe_plan(pat, True)["sym_mult"] == 1  # off unless asked for
 
 
-@pytest.mark.parametrize("tune", TUNINGS[:2], ids=lambda t: f"c{t['chunk']}s{t['split']}k{t['cap']}")
-def test_model_symmetry_broken_plans_match_oracle(tune):
+@pytest.mark.parametrize("tune,direction", [(TUNINGS[0], "above"), (TUNINGS[1], "below")],
+                         ids=["c1s64k64-above", "c64s64k128-below"])
+def test_model_symmetry_broken_plans_match_oracle(tune, direction):
     """Counting one embedding per orbit and scaling gives the oracle's
     labelled count, with hub splits and partial windows forced."""
     hub = xmgen.rmat(7, seed=7)  # lists longer than a split: hub roots are split
@@ -70,5 +77,5 @@ def test_model_symmetry_broken_plans_match_oracle(tune):
                 continue  # the pure-Python model is slow on these there
             want = oracle.count(g, pat)
             for reduced in (True, False):
-                m = Model(describe_plan(pat, reduced, symmetry=True), g, **tune, max_windows=400000)
+                m = Model(describe_plan(pat, reduced, symmetry=direction), g, **tune, max_windows=400000)
                 assert m.run() == want, (pat.name, reduced)
