@@ -170,7 +170,13 @@ def bench_batch256(args):
     g = workloads.batch_graph()
     pats = workloads.batch_patterns()
     G = Graph(g)
-    plans = [Plan(p, reduced=True, graph=G) for p in pats]
+    sym = not args.no_symmetry
+    log("[batch] planning" + (" (symmetry directions from a sampled host walk)" if sym else ""))
+    t_plan = time.time()
+    plans = [Plan(p, reduced=True, graph=G, symmetry=sym) for p in pats]
+    t_plan = time.time() - t_plan
+    n_sym = sum(1 for p in plans if p.describe()["sym_mult"] > 1)
+    log(f"[batch] {n_sym} plans with symmetry breaking, planned in {t_plan:.1f} s")
     s = torch.cuda.Stream()
     log("[batch] autotuning")
     log(f"[batch] dense rows {G.dense_rows_info()}")
@@ -190,7 +196,17 @@ def bench_batch256(args):
     ms_p = timed_plain(plain, s, steps_plain, 1, progress=log)
     plain_counts = [c.results()[0][0] for c in plain]
     assert plain_counts == counts, "batched and plain counts differ"
-    # oracle parity on root subsets of a sample of patterns
+    ms_nosym = None
+    if sym and n_sym:
+        # every embedding enumerated: the same counts
+        log("[batch] batched launch without symmetry breaking")
+        cn = Counter(G, [Plan(p, reduced=True, graph=G) for p in pats], **opts)
+        cn.capture(s)
+        ms_nosym, _ = timed_steps(cn, s, 1, 1, progress=log)
+        assert cn.results()[0] == counts, "symmetry-broken and plain plans differ"
+        del cn
+    # oracle parity on root subsets of a sample of patterns (plans without
+    # symmetry breaking: a subset count is per root)
     log("[batch] oracle root-subset parity")
     rng = np.random.default_rng(7)
     sample_ids = rng.choice(len(pats), size=12, replace=False)
@@ -198,11 +214,12 @@ def bench_batch256(args):
     parity = True
     for i in sample_ids:
         roots = np.sort(rng.choice(g.n, size=256, replace=False)).astype(np.uint32)
-        c = Counter(G, [plans[i]], roots=roots, workspace=ws, **opts)
+        pi = Plan(pats[i], reduced=True, graph=G)
+        c = Counter(G, [pi], roots=roots, **opts)
         c.run(s)
         s.synchronize()
         got = c.results()[0][0]
-        want = oracle.count(g, pats[i], roots=roots, root_vertex=plans[i].root_vertex,
+        want = oracle.count(g, pats[i], roots=roots, root_vertex=pi.root_vertex,
                             threads=threads, mode="B")
         parity = parity and got == want
     total = sum(counts)
@@ -213,10 +230,13 @@ def bench_batch256(args):
         "data": "synthetic",
         "config": {"workload": "batch256_rmat22", "n": g.n, "m": g.m, "patterns": len(pats),
                    "pattern_sizes": {k: sum(1 for p in pats if p.k == k) for k in (3, 4, 5, 6)},
-                   "plan": "reduced", "launch": "one persistent launch, HIP graph, autotuned",
+                   "plan": "reduced, symmetry breaking" if sym else "reduced",
+                   "launch": "one persistent launch, HIP graph, autotuned",
                    "tuned": opts, "dense_rows": G.dense_rows_info()},
         "batched_gpu_ms": round(gpu_b, 3), "plain_ms_per_step": round(ms_p, 3),
         "batched_vs_plain_speedup": round(ms_p / ms_b, 3),
+        "plans_with_symmetry_breaking": n_sym, "planning_s": round(t_plan, 1),
+        "no_symmetry_ms_per_step": None if ms_nosym is None else round(ms_nosym, 3),
         "tune": trec, "counts_sum": str(total), "batched_equals_plain": True,
         "oracle_root_subset_parity": parity, "oracle_parity_patterns": len(sample_ids),
     }

@@ -132,12 +132,28 @@ int xm_graph_info(const xm_graph_t* g, uint32_t* n, uint32_t* m,
  *                      data graph; only the last vertex is counted, not
  *                      enumerated;
  * optionally OR'ed with XM_PLAN_ROOT(v) to force pattern vertex v as the
- * plan's start vertex (needed for root-subset counting).
+ * plan's start vertex (needed for root-subset counting), and with
+ *   XM_PLAN_SYMMETRY   symmetry breaking (the symmetry destruction that the
+ *                      related-work section says XMiner uses, made exact):
+ *                      with H the automorphisms of the pattern that map the
+ *                      enumerated vertices (plus the counted leaf when the
+ *                      leaf group is one vertex) onto themselves, the plan
+ *                      counts one partial match per H-orbit and the launch
+ *                      scales the total by the orbit size, so counts are the
+ *                      same labelled counts; a pattern without such
+ *                      automorphisms gets a plain plan.  xm_count refuses
+ *                      these plans with a root subset or listing;
+ *   XM_PLAN_SYM_BELOW  with XM_PLAN_SYMMETRY: keep per orbit the partial
+ *                      match whose first conditioned vertex has the largest
+ *                      image instead of the smallest (both exact; which
+ *                      enumerates less depends on the graph).
  * g (nullable) supplies degree statistics used as cover weights; with g NULL
  * the plan uses unit weights.  No device work is done.
  * ------------------------------------------------------------------------- */
 #define XM_PLAN_REDUCED 0x1u
 #define XM_PLAN_UNREDUCED 0x2u
+#define XM_PLAN_SYMMETRY 0x4u
+#define XM_PLAN_SYM_BELOW 0x8u
 #define XM_PLAN_ROOT(v) ((((uint32_t)(v)) + 1u) << 8)
 int xm_plan(uint32_t k, uint32_t n_arcs, const uint8_t* arcs, uint32_t flags,
             const xm_graph_t* g, xm_plan_t** out);
@@ -205,7 +221,9 @@ typedef struct xm_count_opts {
     uint32_t waves_per_cu;  /* resident waves per compute unit (default 16) */
     /* root subset: device array of n_roots node ids (< n, distinct); when
        non-NULL only these nodes are tried as images of the plan's start
-       vertex (xm_plan_root_vertex).  Counts are then exact partial sums. */
+       vertex (xm_plan_root_vertex).  Counts are then exact partial sums.
+       Plans with symmetry breaking (sym_mult > 1) are refused here:
+       XM_ERR_INVALID. */
     const uint32_t* roots_dev;
     uint32_t n_roots;
     uint32_t reserved0;
@@ -239,8 +257,8 @@ typedef struct xm_count_opts {
        zeroed by the launch) receives the number of embeddings found, which
        may exceed list_cap (then only list_cap rows were written).  Needs
        n_plans = 1 and a plan whose leaf group is a single vertex (every
-       XM_PLAN_UNREDUCED plan); XM_ERR_INVALID otherwise.  Counts are
-       written as usual. */
+       XM_PLAN_UNREDUCED plan) without symmetry breaking; XM_ERR_INVALID
+       otherwise.  Counts are written as usual. */
     uint32_t* list_dev;
     uint64_t list_cap;
     unsigned long long* list_count_dev;
