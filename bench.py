@@ -4,11 +4,12 @@
 Workload (default): R-MAT scale 16 (65,536 nodes, ~955K arcs after removing
 repeats and loops, (a,b,c,d) = (.57,.19,.19,.05), seed 0), uint32 out+in CSR
 resident in HBM, and four patterns: feed-forward triangle, directed 3-cycle,
-bi-fan, directed 4-cycle.  One step counts all four with their reduced,
-symmetry-broken plans (one embedding per automorphism orbit, scaled by the
-orbit size: the same labelled counts) in one persistent launch, replayed as a
-HIP graph.  The same step is also timed without symmetry breaking, as plain
-per-pattern launches and with unreduced plans.
+bi-fan, directed 4-cycle.  The graph is stored with its nodes renumbered by
+decreasing degree (load time, untimed).  One step counts all four with their
+reduced, symmetry-broken plans (one embedding per automorphism orbit, scaled
+by the orbit size: the same labelled counts) in one persistent launch,
+replayed as a HIP graph.  The same step is also timed without symmetry
+breaking, as plain per-pattern launches and with unreduced plans.
 
 Prints one JSON line (see the repository's benchmark contract).  Only the
 `cpu_baseline` leg calls the oracle, on a bounded root sample.
@@ -449,6 +450,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip plain/unreduced timings")
     ap.add_argument("--no-symmetry", action="store_true",
                     help="plans without symmetry breaking (every embedding enumerated)")
+    ap.add_argument("--generated-order", action="store_true",
+                    help="store the graph in the generator's node order (default: nodes "
+                         "renumbered by decreasing degree at load, untimed)")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--split", type=int, default=0)
     ap.add_argument("--cap", type=int, default=0)
@@ -497,19 +501,20 @@ def main():
     log("[bench] generating R-MAT scale 16")
     g = xmgen.rmat(16, seed=0)
     pats = [xmgen.named(n) for n in PATTERNS]
-    G = Graph(g, dense_rows=args.dense_rows, row_min=args.row_min)
+    G = Graph(g, dense_rows=args.dense_rows, row_min=args.row_min, order_by_degree=not args.generated_order)
     tune = dict(chunk=args.chunk, split=args.split, cap=args.cap, waves_per_cu=args.waves_per_cu)
     sym = not args.no_symmetry
     red = [Plan(p, reduced=True, graph=G, symmetry=sym) for p in pats]
     unred = [Plan(p, reduced=False, graph=G, symmetry=sym) for p in pats]
-    workload = "rmat16_ffl_c3_bifan_c4_reduced" + ("_sym" if sym else "") + "_batched"
+    workload = ("rmat16_ffl_c3_bifan_c4_reduced" + ("_sym" if sym else "")
+                + ("" if args.generated_order else "_degorder") + "_batched")
     s = torch.cuda.Stream()
 
     # algorithmic work of the four plans (host walk, untimed; with symmetry
     # breaking only the list parts above each bound count)
     log("[bench] algorithmic work (host walk)")
     threads = max(1, min(16, len(os.sched_getaffinity(0))))
-    st = [plan_work(g, p, threads=threads) for p in red]
+    st = [plan_work(G.host, p, threads=threads) for p in red]
     E = sum(x["elements"] for x in st)
     F = sum(x["fetches"] for x in st)
     B_alg = 4 * E + 8 * F + 8 * g.n * len(pats)
@@ -532,7 +537,7 @@ def main():
         cu.capture(s)
         ms_unred, kern_unred = timed_steps(cu, s, max(3, args.steps // 4), 1)
         assert cu.results()[0] == counts
-        E_un = sum(plan_work(g, p, threads=threads)["elements"] for p in unred)
+        E_un = sum(plan_work(G.host, p, threads=threads)["elements"] for p in unred)
         if sym:
             log("[bench] batched reduced without symmetry breaking")
             cn = Counter(G, [Plan(p, reduced=True, graph=G) for p in pats], **tune)
@@ -581,7 +586,8 @@ def main():
                    "n": g.n, "m": g.m, "patterns": PATTERNS,
                    "plan": "reduced, symmetry breaking" if sym else "reduced",
                    "launch": "one persistent launch for 4 patterns, HIP graph replay",
-                   "parallelism": "1 GPU", "dense_rows": G.dense_rows_info()},
+                   "parallelism": "1 GPU", "dense_rows": G.dense_rows_info(),
+                   "node_order": "as generated" if args.generated_order else "by decreasing degree (load time)"},
         "counts": [str(c) for c in counts],
         "counts_match_oracle": gold_ok,
         "kernel_ms": round(kern_ms, 4),

@@ -75,6 +75,14 @@ typedef struct xm_exec_s xm_exec_t; /* an instantiated HIP graph of one xm_count
  *                  to device memory it owns.
  *   XM_VALIDATE    check the rules above on the host (copies device arrays
  *                  back when XM_MEM_DEVICE); failure returns XM_ERR_GRAPH.
+ *   XM_ORDER_BY_DEGREE  (with XM_MEM_HOST) store the graph with its nodes
+ *                  renumbered by decreasing total degree, ties by lower id
+ *                  (xm_graph_node_order gives the renumbering).  Counts do not
+ *                  change; symmetry-broken plans (XM_PLAN_SYMMETRY) compare
+ *                  node ids, and in this order their bounds cut more work.
+ *                  Node ids at the boundary would be the new ones, so
+ *                  xm_count refuses root subsets and listing on such a graph
+ *                  (XM_ERR_INVALID).
  * Exactly one of XM_MEM_DEVICE / XM_MEM_HOST must be set.  The call also
  * builds per-node degree pairs and a hub list on the device (library-owned),
  * and synchronises hip_stream before returning.
@@ -82,6 +90,7 @@ typedef struct xm_exec_s xm_exec_t; /* an instantiated HIP graph of one xm_count
 #define XM_MEM_DEVICE 0x1u
 #define XM_MEM_HOST 0x2u
 #define XM_VALIDATE 0x4u
+#define XM_ORDER_BY_DEGREE 0x8u
 int xm_load_graph(uint32_t n, uint32_t m,
                   const uint32_t* out_off, const uint32_t* out_adj,
                   const uint32_t* in_off, const uint32_t* in_adj,
@@ -89,6 +98,10 @@ int xm_load_graph(uint32_t n, uint32_t m,
 /* Frees the graph; fails with XM_ERR_INVALID while captured launches
  * (xm_exec_t) of it exist. */
 int xm_free_graph(xm_graph_t* g);
+/* The node renumbering of a graph loaded with XM_ORDER_BY_DEGREE: writes n
+ * entries to the host array new_of_old (new_of_old[v] = stored id of the
+ * caller's node v); the identity for any other graph. */
+int xm_graph_node_order(const xm_graph_t* g, uint32_t* new_of_old);
 /* Dense membership rows for long adjacency lists.
  *
  * Every candidate test of Algorithm 2 asks whether a node x lies in the out-

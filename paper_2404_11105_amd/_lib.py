@@ -24,6 +24,7 @@ XM_ERR_GRAPH = -8
 
 XM_MEM_DEVICE = 0x1
 XM_MEM_HOST = 0x2
+XM_ORDER_BY_DEGREE = 0x8
 XM_VALIDATE = 0x4
 XM_PLAN_REDUCED = 0x1
 XM_PLAN_UNREDUCED = 0x2
@@ -66,7 +67,7 @@ class XminerError(RuntimeError):
 
 
 EXPORTS = [
-    "xm_load_graph", "xm_free_graph", "xm_graph_info", "xm_graph_dense_rows", "xm_graph_dense_rows_info",
+    "xm_load_graph", "xm_free_graph", "xm_graph_info", "xm_graph_node_order", "xm_graph_dense_rows", "xm_graph_dense_rows_info",
     "xm_plan", "xm_plan_describe",
     "xm_plan_root_vertex", "xm_free_plan", "xm_plan_work", "xm_workspace_size", "xm_count", "xm_count_capture",
     "xm_exec_launch", "xm_free_exec", "xm_strerror", "xm_last_error", "xm_version",
@@ -87,6 +88,7 @@ def lib():
         L.xm_load_graph.argtypes = [U32, U32, P, P, P, P, U32, P, ctypes.POINTER(P)]
         L.xm_free_graph.argtypes = [P]
         L.xm_graph_info.argtypes = [P, P, P, P, P]
+        L.xm_graph_node_order.argtypes = [P, P]
         L.xm_graph_dense_rows.argtypes = [P, ctypes.c_uint64, U32, P, P]
         L.xm_graph_dense_rows_info.argtypes = [P, P, P, P, P]
         L.xm_plan.argtypes = [U32, U32, P, U32, P, ctypes.POINTER(P)]

@@ -44,26 +44,44 @@ class Graph:
     DEFAULT_ROW_MIN = 64
 
     def __init__(self, digraph, device: str = "cuda", validate: bool = False, stream=None,
-                 dense_rows: int | None = None, row_min: int | None = None):
+                 dense_rows: int | None = None, row_min: int | None = None, order_by_degree: bool = False):
         import torch
         self.n = int(digraph.n)
         self.m = int(digraph.m)
         self.device = torch.device(device)
         arrays = (digraph.out_off, digraph.out_adj, digraph.in_off, digraph.in_adj)
-        if all(isinstance(x, torch.Tensor) for x in arrays):
-            # already device-resident int32 tensors holding uint32 values
-            self.tensors = [x.to(self.device).contiguous() for x in arrays]
+        h = ctypes.c_void_p()
+        flags = _lib.XM_VALIDATE if validate else 0
+        if order_by_degree:
+            # the library renumbers and owns the device copy (XM_ORDER_BY_DEGREE)
+            if any(isinstance(x, torch.Tensor) for x in arrays):
+                raise ValueError("order_by_degree needs host (numpy) CSR arrays")
+            host = [np.ascontiguousarray(x, dtype=np.uint32) for x in arrays]
+            host = [a if a.size else np.zeros(1, dtype=np.uint32) for a in host]
+            self.tensors = []
+            flags |= _lib.XM_MEM_HOST | _lib.XM_ORDER_BY_DEGREE
+            ptrs = [a.ctypes.data_as(ctypes.c_void_p) for a in host]
+        else:
+            if all(isinstance(x, torch.Tensor) for x in arrays):
+                # already device-resident int32 tensors holding uint32 values
+                self.tensors = [x.to(self.device).contiguous() for x in arrays]
+            else:
+                self.tensors = [_u32_tensor(x, self.device) for x in arrays]
+            flags |= _lib.XM_MEM_DEVICE
+            ptrs = [ctypes.c_void_p(t.data_ptr()) for t in self.tensors]
+        self.nbytes = 4 * (2 * (self.n + 1) + 2 * self.m)
+        with torch.cuda.device(self.device):
+            check(lib().xm_load_graph(self.n, self.m, *ptrs, flags, _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+        self.order_by_degree = order_by_degree
+        # host CSR in the stored node order, kept for planning estimates and
+        # the host work walk (None for device-only input)
+        if order_by_degree:
+            self.host = _renumbered(digraph, self.node_order())
+        elif all(isinstance(x, torch.Tensor) for x in arrays):
             self.host = None
         else:
-            self.tensors = [_u32_tensor(x, self.device) for x in arrays]
-            self.host = digraph  # host CSR, kept for planning estimates
-        self.nbytes = sum(t.numel() * 4 for t in self.tensors)
-        h = ctypes.c_void_p()
-        flags = _lib.XM_MEM_DEVICE | (_lib.XM_VALIDATE if validate else 0)
-        with torch.cuda.device(self.device):
-            check(lib().xm_load_graph(self.n, self.m, *[ctypes.c_void_p(t.data_ptr()) for t in self.tensors],
-                                      flags, _stream_ptr(stream), ctypes.byref(h)))
-        self.handle = h
+            self.host = digraph
         self.set_dense_rows(self.DEFAULT_ROW_BYTES if dense_rows is None else dense_rows,
                             self.DEFAULT_ROW_MIN if row_min is None else row_min, stream)
 
@@ -82,6 +100,13 @@ class Graph:
                     check(rc)
                     return t.value
                 budget //= 2
+
+    def node_order(self) -> np.ndarray:
+        """new_of_old: the stored id of every node (the identity unless the
+        graph was loaded with order_by_degree)."""
+        out = np.empty(self.n, dtype=np.uint32)
+        check(lib().xm_graph_node_order(self.handle, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
 
     def dense_rows_info(self) -> dict:
         t, no, ni, b = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint64()
@@ -105,6 +130,27 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+def _renumbered(digraph, new_of_old):
+    """Host CSR of digraph with node v renamed new_of_old[v] (lists sorted)."""
+    import types
+    n = int(digraph.n)
+    off = np.asarray(digraph.out_off, dtype=np.int64)
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(off))
+    dst = np.asarray(digraph.out_adj, dtype=np.int64)
+    new = np.asarray(new_of_old, dtype=np.int64)
+    s2, d2 = new[src], new[dst]
+
+    def csr(a, b):
+        o = np.lexsort((b, a))
+        offs = np.zeros(n + 1, dtype=np.uint32)
+        offs[1:] = np.cumsum(np.bincount(a, minlength=n))
+        return offs, b[o].astype(np.uint32)
+
+    oo, oa = csr(s2, d2)
+    io, ia = csr(d2, s2)
+    return types.SimpleNamespace(n=n, m=int(digraph.m), out_off=oo, out_adj=oa, in_off=io, in_adj=ia)
 
 
 class Plan:

@@ -31,6 +31,7 @@ struct xm_graph_s {
     std::vector<uint2> hub_deg;     // host: (out, in) degree of each hub
     uint32_t max_out = 0, max_in = 0;
     std::vector<uint2> hdeg;        // host: (out, in) degree per node
+    std::vector<uint32_t> new_of_old;  // XM_ORDER_BY_DEGREE: the renumbering (empty: none)
     // dense membership rows of long lists (xm_graph_dense_rows)
     uint32_t* rows = nullptr;       // device, owned: out rows, then in rows
     uint2* row_of = nullptr;        // device, owned: per node (out row, in row)
@@ -156,6 +157,10 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
         if (D.e >= 2) splittable++;
         // a symmetry-broken plan counts one embedding per orbit: neither the
         // embeddings of a root subset nor a listing can be read from it
+        if (!g->new_of_old.empty() && o && o->roots_dev)
+            return fail(XM_ERR_INVALID, "root subsets need a graph loaded without XM_ORDER_BY_DEGREE");
+        if (!g->new_of_old.empty() && full_opts && o->list_dev)
+            return fail(XM_ERR_INVALID, "listing needs a graph loaded without XM_ORDER_BY_DEGREE");
         if (D.sym_mult > 1 && o && o->roots_dev)
             return fail(XM_ERR_INVALID, "root subsets need plans without XM_PLAN_SYMMETRY");
         if (D.sym_mult > 1 && full_opts && o->list_dev)
@@ -387,7 +392,10 @@ int xm_load_graph(uint32_t n, uint32_t m, const uint32_t* out_off, const uint32_
         return fail(XM_ERR_INVALID, "CSR array is NULL");
     bool dev_mem = (flags & XM_MEM_DEVICE) != 0, host_mem = (flags & XM_MEM_HOST) != 0;
     if (dev_mem == host_mem) return fail(XM_ERR_INVALID, "set exactly one of XM_MEM_DEVICE / XM_MEM_HOST");
-    if (flags & ~(XM_MEM_DEVICE | XM_MEM_HOST | XM_VALIDATE)) return fail(XM_ERR_INVALID, "unknown flag");
+    if (flags & ~(XM_MEM_DEVICE | XM_MEM_HOST | XM_VALIDATE | XM_ORDER_BY_DEGREE))
+        return fail(XM_ERR_INVALID, "unknown flag");
+    const bool reorder = (flags & XM_ORDER_BY_DEGREE) != 0;
+    if (reorder && !host_mem) return fail(XM_ERR_INVALID, "XM_ORDER_BY_DEGREE needs XM_MEM_HOST");
     hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     xm_graph_t* g = new (std::nothrow) xm_graph_s;
     if (!g) return fail(XM_ERR_OOM, "host allocation");
@@ -464,11 +472,46 @@ int xm_load_graph(uint32_t n, uint32_t m, const uint32_t* out_off, const uint32_
                 }
             }
     }
+    std::vector<uint32_t> roa, ria;  // renumbered lists (XM_ORDER_BY_DEGREE)
+    if (reorder) {
+        // new ids by decreasing total degree (ties: lower old id first); each
+        // list is renumbered and sorted again
+        std::vector<uint32_t> by_deg(n);
+        for (uint32_t v = 0; v < n; v++) by_deg[v] = v;
+        auto tot = [&](uint32_t v) { return (uint64_t)(ho[v + 1] - ho[v]) + (hi[v + 1] - hi[v]); };
+        std::stable_sort(by_deg.begin(), by_deg.end(), [&](uint32_t a, uint32_t b) { return tot(a) > tot(b); });
+        g->new_of_old.assign(n, 0);
+        for (uint32_t i = 0; i < n; i++) g->new_of_old[by_deg[i]] = i;
+        const std::vector<uint32_t>& nw = g->new_of_old;
+        auto renumber = [&](const std::vector<uint32_t>& off, const uint32_t* adj, std::vector<uint32_t>& noff,
+                            std::vector<uint32_t>& nadj) {
+            noff.assign(n + 1, 0);
+            for (uint32_t i = 0; i < n; i++) noff[i + 1] = noff[i] + (off[by_deg[i] + 1] - off[by_deg[i]]);
+            nadj.resize(std::max<uint32_t>(m, 1));
+            for (uint32_t i = 0; i < n; i++) {
+                const uint32_t v = by_deg[i];
+                uint32_t* d = nadj.data() + noff[i];
+                for (uint32_t k = off[v]; k < off[v + 1]; k++) *d++ = nw[adj[k]];
+                std::sort(nadj.data() + noff[i], nadj.data() + noff[i + 1]);
+            }
+        };
+        std::vector<uint32_t> no, ni;
+        renumber(ho, out_adj, no, roa);
+        renumber(hi, in_adj, ni, ria);
+        ho.swap(no);
+        hi.swap(ni);
+    }
     if (host_mem) {
         void* p[4] = {nullptr, nullptr, nullptr, nullptr};
         size_t sz[4] = {(size_t)(n + 1) * 4, (size_t)std::max<uint32_t>(m, 1) * 4, (size_t)(n + 1) * 4,
                         (size_t)std::max<uint32_t>(m, 1) * 4};
         const void* src[4] = {out_off, out_adj, in_off, in_adj};
+        if (reorder) {
+            src[0] = ho.data();
+            src[1] = roa.data();
+            src[2] = hi.data();
+            src[3] = ria.data();
+        }
         size_t cp[4] = {(size_t)(n + 1) * 4, (size_t)m * 4, (size_t)(n + 1) * 4, (size_t)m * 4};
         g->owns_csr = true;
         for (int i = 0; i < 4; i++) {
@@ -689,6 +732,12 @@ int xm_graph_dense_rows_info(const xm_graph_t* g, uint32_t* min_len, uint32_t* n
     if (n_out_rows) *n_out_rows = on ? g->n_rows_out : 0;
     if (n_in_rows) *n_in_rows = on ? g->n_rows_in : 0;
     if (bytes) *bytes = on ? (uint64_t)(g->n_rows_out + g->n_rows_in) * g->row_words * 4 : 0;
+    return XM_OK;
+}
+
+int xm_graph_node_order(const xm_graph_t* g, uint32_t* new_of_old) {
+    if (!g || !new_of_old) return fail(XM_ERR_INVALID, "NULL argument");
+    for (uint32_t v = 0; v < g->n; v++) new_of_old[v] = g->new_of_old.empty() ? v : g->new_of_old[v];
     return XM_OK;
 }
 

@@ -314,3 +314,32 @@ def test_symmetry_rejects_root_subsets_and_listing(xa):
     c.run()
     got, st = c.results()
     assert got == [oracle.count(g, xmgen.named("ffl"))] and st == [0]
+
+
+def test_degree_order_keeps_counts(xa):
+    """A graph stored with its nodes renumbered by decreasing degree gives the
+    oracle's counts with and without symmetry breaking (either direction),
+    and refuses root subsets and listing."""
+    from tests.cases import symmetric_patterns
+    pats = [xmgen.named(n) for n in ["ffl", "c3", "bifan", "c4", "tt4p", "c5chord", "mixed_star"]]
+    pats += symmetric_patterns()[7:13]
+    for g in (xmgen.rmat(9, seed=3), xmgen.uniform_digraph(300, 2400, 5)):
+        banner(f"degree order on {g.name}, {len(pats)} patterns")
+        G = xa.Graph(g, order_by_degree=True)
+        new = G.node_order()
+        assert np.array_equal(np.sort(new), np.arange(g.n, dtype=np.uint32))
+        deg = np.diff(g.out_off.astype(np.int64)) + np.diff(g.in_off.astype(np.int64))
+        by_new = np.empty(g.n, dtype=np.int64)
+        by_new[new] = deg
+        assert np.all(np.diff(by_new) <= 0), "stored ids are not in decreasing degree order"
+        want = [oracle.count(g, p, threads=8, mode="B") for p in pats]
+        for reduced in (True, False):
+            for symmetry in (False, "above", "below", True):
+                assert run(xa, g, pats, G=G, reduced=reduced, symmetry=symmetry) == want, (reduced, symmetry)
+        p = xa.Plan(xmgen.named("ffl"), graph=G)
+        with pytest.raises(Exception):
+            c = xa.Counter(G, [p], roots=np.arange(10, dtype=np.uint32))
+            c.run()
+        with pytest.raises(Exception):
+            c = xa.Counter(G, [xa.Plan(xmgen.named("ffl"), reduced=False, graph=G)], list_cap=100)
+            c.run()
