@@ -1036,6 +1036,15 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
     const uint32_t total_chunks = chunks_per_plan * a.n_plans;
     Lvl F0 = lvl_arrays(C.scr, a.cap, 0);
     uint32_t taken = 0;
+    // root items come from kQueues interleaved cursors (cursor q: items q,
+    // q + kQueues, ...), so the grabs spread over several words and every
+    // cursor still walks the items in order; a wave starts at its home
+    // cursor and moves on once one runs dry
+    uint32_t rq = home, rtried = 0;
+    // a wave counts as active from its first task until the queues run dry
+    // (and again while it runs a donated task), not per task
+    bool active = true;
+    if (C.lane == 0) atomicAdd(&a.ctl[kCtlActive], 1u);
     for (;;) {
         // ---- take a task
         uint32_t kind = 2, item = 0;
@@ -1065,13 +1074,21 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
                     }
                 }
             }
-            if (!stop && kind == 2) {
-                uint32_t c = atomicAdd(&a.ctl[kCtlRootCursor], 1u);
-                if (c < total_chunks) {
+            while (!stop && kind == 2 && rtried < kQueues) {
+                const uint32_t c = atomicAdd(&a.ctl[kCtlRootCursor0 + 32 * rq], 1u);
+                const uint64_t it = (uint64_t)rq + (uint64_t)kQueues * c;
+                if (it < total_chunks) {
                     kind = 1;
-                    item = c;
+                    item = (uint32_t)it;
+                } else {
+                    rq = (rq + 1) % kQueues;
+                    rtried++;
                 }
             }
+        }
+        if (C.lane == 0 && kind == 2 && active) {
+            atomicSub(&a.ctl[kCtlActive], 1u);
+            active = false;
         }
         if (C.lane == 0 && kind == 2 && !stop) {
             // queues drained: wait for donated work while any wave still holds a
@@ -1099,7 +1116,10 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
             }
             atomicSub(&a.ctl[kCtlIdle], 1u);
         }
-        if (C.lane == 0 && kind != 2) atomicAdd(&a.ctl[kCtlActive], 1u);
+        if (C.lane == 0 && kind == 3) {
+            atomicAdd(&a.ctl[kCtlActive], 1u);
+            active = true;
+        }
         kind = uni(__shfl(kind, 0, 64));
         item = uni(__shfl(item, 0, 64));
         if (kind == 2) break;
@@ -1177,7 +1197,6 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
         wave_sync();
         if (n0) explore<NONLIN>(C, n0, start);
         flush(C);
-        if (C.lane == 0) atomicSub(&a.ctl[kCtlActive], 1u);
     }
 }
 

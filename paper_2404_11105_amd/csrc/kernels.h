@@ -22,18 +22,18 @@ constexpr uint32_t kDonWords = 8;  // donated task: plan | depth << 16, ready fl
 constexpr uint32_t kDonCap = 1u << 18;  // donated-task slots per launch
 
 enum Ctl : uint32_t {
-    kCtlRootCursor = 0,   // next root chunk
     kCtlCancelled = 3,    // a wave saw the cancel flag
     kCtlQueueFull = 4,    // split queue overflow (cannot happen with a sized workspace)
     kCtlBadPlan = 5,      // a level had more constraints than the layout holds (cannot happen)
     kCtlSplitHead0 = 8,   // [kQueues]: next item of split queue q
     kCtlSplitCount0 = 16, // [kQueues]: items the split kernel wrote to queue q
     // the words idle waves poll sit on cache lines of their own
-    kCtlActive = 64,      // waves holding a task
+    kCtlActive = 64,      // waves in a work phase (from their first task until the queues ran dry)
     kCtlIdle = 96,        // waves waiting for donated tasks
     kCtlDonHead = 128,    // next donated task to take
     kCtlDonTail = 160,    // donated-task slots reserved
-    kCtlWords = 192
+    kCtlRootCursor0 = 192,  // [kQueues], 32 words apart: cursor q hands out root items q, q + 8, ...
+    kCtlWords = 192 + 32 * kQueues
 };
 
 struct DevGraph {
