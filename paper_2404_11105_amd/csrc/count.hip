@@ -1028,6 +1028,8 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
     const uint64_t gw = (uint64_t)blockIdx.x * kWavesPerBlock + wid;
     C.scr = a.scratch + gw * (uint64_t)a.wave_words;
     C.acc_lo = C.acc_hi = 0;
+    C.pi = 0;
+    C.P = a.plans;
     // this wave's home split queue: the XCD its block runs on (blocks go to
     // the 8 XCDs round-robin), so a hub's sub-range tasks share one L2
     const uint32_t home = blockIdx.x % kQueues;
@@ -1124,10 +1126,18 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
         item = uni(__shfl(item, 0, 64));
         if (kind == 2) break;
         uint32_t n0 = 0, start = 1;
+        // counts of consecutive tasks of one plan stay in the lanes'
+        // accumulators: flush only when the plan changes (and at the end)
+        auto set_plan = [&](uint32_t pi) {
+            if (pi != C.pi) {
+                flush(C);
+                C.pi = pi;
+            }
+            C.P = a.plans + C.pi;
+        };
         if (kind == 0) {
             uint4 it = a.split_items[item];
-            C.pi = uni(it.x);
-            C.P = a.plans + C.pi;
+            set_plan(uni(it.x));
             if (C.lane == 0) {
                 F0.node[0] = it.y;
                 F0.parent[0] = it.z;
@@ -1149,8 +1159,7 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
             ready = uni(__shfl(ready, 0, 64));
             __atomic_thread_fence(__ATOMIC_ACQUIRE);  // every lane reads the entry after its ready flag
             const uint32_t head = ready ? uni(__atomic_load_n(&ent[0], __ATOMIC_RELAXED)) : (1u << 16);
-            C.pi = head & 0xFFFFu;
-            C.P = a.plans + C.pi;
+            set_plan(head & 0xFFFFu);
             start = head >> 16;
             if (ready && C.lane < start) {
                 Lvl F = lvl_arrays(C.scr, a.cap, C.lane);
@@ -1162,8 +1171,7 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
             n0 = ready ? 1u : 0u;
         } else {
             // interleave plans so that all of them start on the low (hub) ids
-            C.pi = uni(item % a.n_plans);
-            C.P = a.plans + C.pi;
+            set_plan(uni(item % a.n_plans));
             const uint32_t ci = item / a.n_plans;
             // chunk ci takes the roots ci, ci + chunks, ci + 2 chunks, ...: long
             // lists cluster at low ids on power-law generators, and striding
@@ -1196,8 +1204,8 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
         }
         wave_sync();
         if (n0) explore<NONLIN>(C, n0, start);
-        flush(C);
     }
+    flush(C);
 }
 
 // Hub roots whose first-level list is longer than `split` become several
