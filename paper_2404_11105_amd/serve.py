@@ -57,19 +57,24 @@ class Request:
 class GpuBackend:
     """Runs micro-batches with the HIP library on torch streams."""
 
-    def __init__(self, graphs: dict, opts: dict | None = None):
+    def __init__(self, graphs: dict, opts: dict | None = None, symmetry: bool = True):
         import torch
         self.torch = torch
         self.graphs = graphs
         self.opts = dict(opts or {})
         self.plans = {}
+        # unpinned requests count with symmetry-broken plans (same counts);
+        # the fixed side keeps planning free of host walks per request
+        self.symmetry = symmetry
 
     def plan(self, graph_id, pattern, pin_vertex=None):
         from .api import Plan
         key = (graph_id, pattern.k, pattern.arcs, pin_vertex)
         p = self.plans.get(key)
         if p is None:
-            p = Plan(pattern, reduced=True, graph=self.graphs[graph_id], root_vertex=pin_vertex)
+            # a pinned request counts a root subset: no symmetry breaking there
+            sym = "above" if self.symmetry and pin_vertex is None else False
+            p = Plan(pattern, reduced=True, graph=self.graphs[graph_id], root_vertex=pin_vertex, symmetry=sym)
             self.plans[key] = p
         return p
 
