@@ -463,6 +463,7 @@ def main():
                          "renumbered by decreasing degree at load, untimed)")
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--split", type=int, default=0)
+    ap.add_argument("--split-work", type=int, default=0)
     ap.add_argument("--cap", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--row-min", type=int, default=None,
@@ -510,7 +511,8 @@ def main():
     g = xmgen.rmat(16, seed=0)
     pats = [xmgen.named(n) for n in PATTERNS]
     G = Graph(g, dense_rows=args.dense_rows, row_min=args.row_min, order_by_degree=not args.generated_order)
-    tune = dict(chunk=args.chunk, split=args.split, cap=args.cap, waves_per_cu=args.waves_per_cu)
+    tune = dict(chunk=args.chunk, split=args.split, split_work=args.split_work, cap=args.cap,
+                waves_per_cu=args.waves_per_cu)
     sym = not args.no_symmetry
     red = [Plan(p, reduced=True, graph=G, symmetry=sym) for p in pats]
     unred = [Plan(p, reduced=False, graph=G, symmetry=sym) for p in pats]

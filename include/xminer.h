@@ -228,10 +228,13 @@ typedef struct xm_count_opts {
     uint32_t split;         /* a root whose first-level candidate list has L1
                                entries is split into stealable sub-ranges of
                                min(split, split_work / L1) entries (at least 1)
-                               when L1 exceeds that size (default 64, >= 64) */
+                               when L1 exceeds that size (default 64, >= 64);
+                               for a plan with one enumerated level below the
+                               root, 8 x split (at most cap) and 16 x split_work */
     uint32_t cap;           /* per-level candidate buffer entries (default 4096,
                                at least split) */
-    uint32_t waves_per_cu;  /* resident waves per compute unit (default 16) */
+    uint32_t waves_per_cu;  /* resident waves per compute unit (default: as many
+                               as the kernel's registers and LDS allow, at most 32) */
     /* root subset: device array of n_roots node ids (< n, distinct); when
        non-NULL only these nodes are tried as images of the plan's start
        vertex (xm_plan_root_vertex).  Counts are then exact partial sums.

@@ -1191,7 +1191,7 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
             if (ok && C.P->e >= 2) {
                 uint32_t l = level1_len(a.g, C.P, r);
                 // longer lists were queued as sub-ranges by the split kernel
-                ok = l > 0 && l <= item_size(l, a.split, a.split_work);
+                ok = l > 0 && l <= plan_item_size(l, C.P->e, a.split, a.split_work, a.cap);
             }
             uint64_t m = __ballot(ok);
             if (ok) {
@@ -1224,7 +1224,7 @@ __global__ void split_kernel(KArgs a) {
         uint2 d = a.g.deg[r];
         if (d.x < P->root_dout || d.y < P->root_din) continue;
         uint32_t len = level1_len(a.g, P, r);
-        const uint32_t sz = item_size(len, a.split, a.split_work);
+        const uint32_t sz = plan_item_size(len, P->e, a.split, a.split_work, a.cap);
         if (len <= sz) continue;
         uint32_t nit = (len + sz - 1) / sz;
         // all tasks of one root go to one queue (one XCD's L2)

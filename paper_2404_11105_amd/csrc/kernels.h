@@ -125,6 +125,21 @@ __host__ __device__ inline uint32_t item_size(uint32_t L1, uint32_t split, uint3
     return s > floor_s ? s : floor_s;
 }
 
+// Sub-range size for a plan with e enumerated levels (root included).  A
+// plan with one level below the root spends one leaf count per first-level
+// candidate, so its sub-ranges are larger (8x the candidates, 16x the work
+// target, at most cap) than those of deeper plans, whose candidates each
+// carry a subtree.  The split kernel, the count kernel's root filter and the
+// host's queue sizing all use this.
+__host__ __device__ inline uint32_t plan_item_size(uint32_t L1, uint32_t e, uint32_t split, uint32_t split_work,
+                                                   uint32_t cap) {
+    if (e == 2) {
+        split = split <= cap / 8 ? split * 8 : (cap > split ? cap : split);
+        split_work = split_work <= (0xFFFFFFFFu >> 4) ? split_work << 4 : 0xFFFFFFFFu;
+    }
+    return item_size(L1, split, split_work);
+}
+
 // LDS words per wave: `rows` bound levels (the largest enumerated depth of
 // the batch), the largest constraint count, and the optional parts.
 inline uint32_t lds_words_for(uint32_t rows, uint32_t maxc, bool nonlinear, bool merge) {

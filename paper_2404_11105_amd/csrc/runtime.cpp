@@ -192,8 +192,8 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
     // hub, the root filter and the first-level list length (the shortest list
     // of the level-1 constraints).  When the queue would pass kMaxQueueBytes
     // the task size target split_work doubles for this launch.
-    auto pieces = [&](uint32_t len, uint32_t sw) -> uint64_t {
-        uint32_t sz = xm::item_size(len, L.split, sw);
+    auto pieces = [&](uint32_t len, uint32_t sw, uint32_t e) -> uint64_t {
+        uint32_t sz = xm::plan_item_size(len, e, L.split, sw, L.cap);
         return len > sz ? (len + sz - 1) / sz : 0;
     };
     // per queue: a root's tasks go to queue (its index in the hub list or
@@ -215,7 +215,7 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
                     if (d.x < D.root_dout || d.y < D.root_din) continue;
                     uint32_t L1 = 0xFFFFFFFFu;
                     for (int c = 0; c < D.lvl[1].n_cons; c++) L1 = std::min(L1, D.lvl[1].cons_dir[c] ? d.y : d.x);
-                    const uint64_t pc = pieces(L1, sw);
+                    const uint64_t pc = pieces(L1, sw, D.e);
                     tot += pc;
                     qc[k % xm::kQueues] += pc;
                 }
@@ -223,7 +223,8 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
             return tot;
         }
         if (o && o->roots_dev) {  // subset degrees are not known on the host: bound them
-            const uint64_t per = pieces(max_list, sw) * splittable;
+            // the smaller sub-ranges (deeper plans) bound every plan's count
+            const uint64_t per = pieces(max_list, sw, 3) * splittable;
             for (uint32_t q = 0; q < xm::kQueues; q++)
                 qc[q] = (o->n_roots > q ? ((uint64_t)o->n_roots - q + xm::kQueues - 1) / xm::kQueues : 0) * per;
             return (uint64_t)o->n_roots * per;
@@ -236,7 +237,7 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
                 if (d.x < D.root_dout || d.y < D.root_din) continue;
                 uint32_t L1 = 0xFFFFFFFFu;
                 for (int c = 0; c < D.lvl[1].n_cons; c++) L1 = std::min(L1, D.lvl[1].cons_dir[c] ? d.y : d.x);
-                const uint64_t pc = pieces(L1, sw);
+                const uint64_t pc = pieces(L1, sw, D.e);
                 tot += pc;
                 qc[h % xm::kQueues] += pc;
             }

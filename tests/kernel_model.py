@@ -48,8 +48,13 @@ class Model:
         return min(self.lst(r, d)[1] for j, d in L["cons"])
 
     def item_size(self, L1):
-        s = self.split_work // L1 if L1 else self.split
-        s = max(1, min(s, self.split))
+        split, split_work = self.split, self.split_work
+        if self.P["e"] == 2:
+            # one level below the root: larger sub-ranges (at most cap)
+            split = split * 8 if split <= self.cap // 8 else max(self.cap, split)
+            split_work = min(split_work * 16, 0xFFFFFFFF)
+        s = split_work // L1 if L1 else split
+        s = max(1, min(s, split))
         return max(s, -(-L1 // 4096))
 
     def deg(self, x):
