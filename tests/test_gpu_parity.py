@@ -196,6 +196,10 @@ def test_config2_full_size(xa):
         banner(f"  symmetry-broken plans, {direction}")
         assert run(xa, g, pats, G=G, reduced=True, symmetry=direction) == want
         assert run(xa, g, pats, G=G, reduced=False, symmetry=direction) == want
+    banner("  graph in degree order, symmetry side chosen by the sampled walk")
+    Gd = xa.Graph(g, order_by_degree=True)
+    assert run(xa, g, pats, G=Gd, reduced=True, symmetry=True) == want
+    assert run(xa, g, pats, G=Gd, reduced=True) == want
 
 
 
