@@ -65,3 +65,12 @@ def symmetric_patterns():
                     break
     return out
 
+
+def symmetric_patterns_large():
+    """Larger groups and k up to 7: a directed 6-cycle (|Aut| 6), three
+    2-paths from one vertex (|Aut| 6) and a star of four bidirected edges
+    (|Aut| 24).  The oracle is slow on them beyond small graphs."""
+    P = xmgen.Pattern
+    return [P(6, ((0, 1), (1, 2), (2, 3), (3, 4), (4, 5), (5, 0)), "c6"),
+            P(7, ((0, 1), (1, 2), (0, 3), (3, 4), (0, 5), (5, 6)), "windmill3"),
+            P(5, tuple(x for i in range(1, 5) for x in ((0, i), (i, 0))), "bistar4")]

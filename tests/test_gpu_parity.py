@@ -281,6 +281,21 @@ def test_symmetry_broken_plans_vs_oracle(xa, tune, direction):
             assert run(xa, g, pats, G=G, reduced=reduced, symmetry=direction, **tune) == want, reduced
 
 
+def test_symmetry_large_groups_vs_oracle(xa):
+    """Groups of order 6 and 24 and patterns of up to 7 vertices, on a graph
+    small enough for the oracle: both sides, reduced and unreduced, in the
+    generated and the degree order."""
+    from tests.cases import symmetric_patterns_large
+    pats = symmetric_patterns_large()
+    g = xmgen.uniform_digraph(50, 900, 21)  # dense enough for reciprocal arcs
+    banner(f"symmetry-broken plans, large groups, {g.name}")
+    want = [oracle.count(g, p, threads=8) for p in pats]
+    for G in (xa.Graph(g), xa.Graph(g, order_by_degree=True)):
+        for reduced in (True, False):
+            for direction in ("above", "below"):
+                assert run(xa, g, pats, G=G, reduced=reduced, symmetry=direction) == want, (reduced, direction)
+
+
 def test_symmetry_closed_forms(xa):
     """Complete digraph: n!/(n-k)! for every pattern.  Out-star hub: the
     falling factorial above 2^64 with the reduced plan (its leaf group holds

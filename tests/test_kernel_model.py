@@ -9,7 +9,7 @@ import pytest
 import oracle
 import xmgen
 from paper_2404_11105_amd import describe_plan
-from tests.cases import symmetric_patterns
+from tests.cases import symmetric_patterns, symmetric_patterns_large
 from tests.kernel_model import Model
 
 TUNINGS = [dict(chunk=1, split=64, cap=64), dict(chunk=64, split=64, cap=128, split_work=4096),
@@ -45,7 +45,7 @@ def test_model_random_patterns_small_cap():
 def test_symmetry_multiplier_is_the_orbit_size():
     """With one counted leaf every vertex is conditioned, so the multiplier is
     |Aut(P)| (counted here by brute force); in general it divides it."""
-    for pat in symmetric_patterns():
+    for pat in symmetric_patterns() + symmetric_patterns_large():
         aut = pat.automorphisms()
         for reduced in (True, False):
             d = describe_plan(pat, reduced, symmetry=True)
@@ -72,7 +72,7 @@ def test_model_symmetry_broken_plans_match_oracle(tune, direction):
     hub = xmgen.rmat(7, seed=7)  # lists longer than a split: hub roots are split
     small = xmgen.uniform_digraph(40, 420, 11)
     for g in (hub, small):
-        for pat in symmetric_patterns():
+        for pat in symmetric_patterns() + (symmetric_patterns_large() if g is small else []):
             if g is hub and (pat.k > 4 or pat.name == "mixed_star") and pat.name not in ("k23", "c5"):
                 continue  # the pure-Python model is slow on these there
             want = oracle.count(g, pat)
