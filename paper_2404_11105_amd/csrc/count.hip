@@ -227,6 +227,7 @@ struct Ctx {
     uint32_t* scr;
     uint32_t lane;
     unsigned long long acc_lo, acc_hi;  // per-lane 128-bit partial (leaf groups)
+    bool donated;                       // this wave has handed off work (it then always waits)
 };
 
 // First-level base list length of root r for plan P (shortest constraint list).
@@ -944,6 +945,7 @@ __device__ void maybe_donate(Ctx& C, uint32_t start, uint32_t lv) {
         }
         base = uni(__shfl(base, 0, 64));
         if (base == kSkip) return;  // no room: keep the work
+        C.donated = true;
         if (C.lane < k) {
             uint32_t* ent = a.don + (uint64_t)(base + C.lane) * kDonWords;
             uint32_t idx = n - k + C.lane;
@@ -1030,6 +1032,7 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
     C.acc_lo = C.acc_hi = 0;
     C.pi = 0;
     C.P = a.plans;
+    C.donated = false;
     // this wave's home split queue: the XCD its block runs on (blocks go to
     // the 8 XCDs round-robin), so a hub's sub-range tasks share one L2
     const uint32_t home = blockIdx.x % kQueues;
@@ -1097,7 +1100,11 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
             // task.  At most kMaxWaiters waves wait (the others leave at once),
             // and they poll with growing pauses, so waiting waves do not crowd
             // the cache lines the working waves update.
-            if (atomicAdd(&a.ctl[kCtlIdle], 1u) < kMaxWaiters) {
+            // A wave that donated always waits: a waiter that read the queue
+            // just before a donation was published and the active count just
+            // after its donor finished would leave without it, and the donor
+            // itself then takes its entries (the poll checks the queue first).
+            if (atomicAdd(&a.ctl[kCtlIdle], 1u) < kMaxWaiters || C.donated) {
                 uint32_t nap = 1;
                 for (uint32_t polls = 0; polls < kIdlePolls; polls++) {
                     const uint32_t h = __atomic_load_n(&a.ctl[kCtlDonHead], __ATOMIC_RELAXED);
