@@ -154,8 +154,11 @@ int xm_graph_info(const xm_graph_t* g, uint32_t* n, uint32_t* m,
  *                      counts one partial match per H-orbit and the launch
  *                      scales the total by the orbit size, so counts are the
  *                      same labelled counts; a pattern without such
- *                      automorphisms gets a plain plan.  xm_count refuses
- *                      these plans with a root subset or listing;
+ *                      automorphisms gets a plain plan.  With XM_PLAN_ROOT(v)
+ *                      only automorphisms that fix v are used, so each orbit
+ *                      keeps one image of v and root-subset counts stay
+ *                      exact; without it xm_count refuses such a plan with a
+ *                      root subset.  Listing refuses both;
  *   XM_PLAN_SYM_BELOW  with XM_PLAN_SYMMETRY: keep per orbit the partial
  *                      match whose first conditioned vertex has the largest
  *                      image instead of the smallest (both exact; which
@@ -238,8 +241,8 @@ typedef struct xm_count_opts {
     /* root subset: device array of n_roots node ids (< n, distinct); when
        non-NULL only these nodes are tried as images of the plan's start
        vertex (xm_plan_root_vertex).  Counts are then exact partial sums.
-       Plans with symmetry breaking (sym_mult > 1) are refused here:
-       XM_ERR_INVALID. */
+       Plans with symmetry breaking are refused here (XM_ERR_INVALID) unless
+       they were built with a forced start vertex (XM_PLAN_ROOT). */
     const uint32_t* roots_dev;
     uint32_t n_roots;
     uint32_t reserved0;

@@ -158,8 +158,9 @@ class Plan:
 
     symmetry counts one embedding per orbit of the pattern's automorphisms on
     the enumerated vertices and scales the total by the orbit size (same
-    counts, less work); such a plan cannot count a root subset or list
-    embeddings.  "above" keeps, per orbit, the embedding whose first
+    counts, less work); such a plan cannot list embeddings, and counts a root
+    subset only with a forced root_vertex (then only automorphisms fixing
+    that vertex are used).  "above" keeps, per orbit, the embedding whose first
     conditioned vertex has the smallest image; "below" the largest; True picks
     the one with less estimated work on `graph` (a sampled host walk), or
     "above" without a host copy of the graph."""
@@ -493,13 +494,15 @@ def workspace_bytes(graph: Graph, plans, **opts) -> int:
     return int(ws)
 
 
-def count_anchored(graph: Graph, pattern, vertex: int, nodes, reduced: bool = True, stream=None, **opts):
+def count_anchored(graph: Graph, pattern, vertex: int, nodes, reduced: bool = True, stream=None,
+                   symmetry=False, **opts):
     """Embeddings of `pattern` that map pattern vertex `vertex` to each data
     node in `nodes` (a constant pattern vertex, Definition 2.2's vertex
     constraints): the plan starts at `vertex` and each node is a one-root
-    subset.  Returns one count per node."""
+    subset.  Returns one count per node.  With symmetry, only automorphisms
+    that fix `vertex` are used, so every count stays exact per node."""
     import numpy as np
-    plan = Plan(pattern, reduced=reduced, graph=graph, root_vertex=vertex)
+    plan = Plan(pattern, reduced=reduced, graph=graph, root_vertex=vertex, symmetry=symmetry)
     out = []
     for x in np.asarray(nodes, dtype=np.uint32).reshape(-1):
         c = Counter(graph, [plan], roots=np.array([x], dtype=np.uint32), **opts)

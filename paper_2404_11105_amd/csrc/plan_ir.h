@@ -87,7 +87,8 @@ struct PlanDesc {
     LevelDesc sig[kMaxSig];       // leaf signatures (inj over levels < e)
     uint8_t sig_mult[kMaxSig];    // leaves per signature
     uint8_t order[kMaxK];         // level -> pattern vertex (reporting)
-    uint8_t pad2[5];
+    uint8_t sym_fixes_root;       // 1: the symmetry group fixes the start vertex (root subsets stay exact)
+    uint8_t pad2[4];
     Term terms[kMaxTerms];
     // Every signature mask M used by a term block, with the candidate test of
     // the intersection of those signatures' sets (union of their constraints):

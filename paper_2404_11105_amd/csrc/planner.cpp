@@ -454,7 +454,7 @@ std::vector<Perm> automorphisms(const Pat& p) {
 
 // Sets D.sym_mult and the `gt` masks; drops a reuse whose source was trimmed
 // by a bound the reusing descriptor does not have.
-void apply_symmetry(const Pat& p, PlanDesc& D, bool below) {
+void apply_symmetry(const Pat& p, PlanDesc& D, bool below, bool fix_root) {
     const int nc = (int)D.e + (D.t == 1 ? 1 : 0);  // conditioned positions in level order
     uint32_t cmask = 0;
     int pos_of[kMaxK];
@@ -467,6 +467,9 @@ void apply_symmetry(const Pat& p, PlanDesc& D, bool below) {
     // automorphisms that map that set onto itself
     std::vector<Perm> grp;
     for (const Perm& s : automorphisms(p)) {
+        // with a forced start vertex only automorphisms fixing it: then every
+        // orbit keeps one root image and counts per root stay exact
+        if (fix_root && s[D.order[0]] != D.order[0]) continue;
         uint32_t img = 0;
         for (int v = 0; v < p.k; v++)
             if (cmask & (1u << v)) img |= 1u << s[v];
@@ -476,6 +479,7 @@ void apply_symmetry(const Pat& p, PlanDesc& D, bool below) {
         if (std::find(grp.begin(), grp.end(), r) == grp.end()) grp.push_back(r);
     }
     D.sym_mult = (uint32_t)grp.size();
+    D.sym_fixes_root = fix_root ? 1 : 0;
     uint8_t gt[kMaxK + 1] = {0};  // by position
     for (int i = 0; i < nc && grp.size() > 1; i++) {
         const int v = D.order[i];
@@ -561,8 +565,8 @@ std::string plan_json(const Pat& p, const PlanDesc& D, const CoverReport& cr, bo
         o += buf;
         s += o;
     }
-    std::snprintf(buf, sizeof buf, "],\"t\":%u,\"linear\":%u,\"seg_src\":%u,\"sym_mult\":%u,\"terms\":[", D.t,
-                  D.linear, D.seg_src, D.sym_mult ? D.sym_mult : 1u);
+    std::snprintf(buf, sizeof buf, "],\"t\":%u,\"linear\":%u,\"seg_src\":%u,\"sym_mult\":%u,\"sym_fixes_root\":%u,\"terms\":[",
+                  D.t, D.linear, D.seg_src, D.sym_mult ? D.sym_mult : 1u, (unsigned)D.sym_fixes_root);
     s += buf;
     for (uint32_t i = 0; i < D.n_terms; i++) {
         std::snprintf(buf, sizeof buf, "%s{\"coef\":%d,\"masks\":[", i ? "," : "", D.terms[i].coef);
@@ -778,7 +782,7 @@ int build_plan(uint32_t k, uint32_t n_arcs, const uint8_t* arcs, uint32_t flags,
         }
     }
     D.sym_mult = 1;
-    if (flags & 0x4u) apply_symmetry(p, D, (flags & 0x8u) != 0);
+    if (flags & 0x4u) apply_symmetry(p, D, (flags & 0x8u) != 0, forced >= 0);
     // packed constraint fields read by the kernel
     auto pack = [](LevelDesc& L) {
         L.dir_mask = 0;

@@ -161,8 +161,9 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
             return fail(XM_ERR_INVALID, "root subsets need a graph loaded without XM_ORDER_BY_DEGREE");
         if (!g->new_of_old.empty() && full_opts && o->list_dev)
             return fail(XM_ERR_INVALID, "listing needs a graph loaded without XM_ORDER_BY_DEGREE");
-        if (D.sym_mult > 1 && o && o->roots_dev)
-            return fail(XM_ERR_INVALID, "root subsets need plans without XM_PLAN_SYMMETRY");
+        if (D.sym_mult > 1 && !D.sym_fixes_root && o && o->roots_dev)
+            return fail(XM_ERR_INVALID,
+                        "root subsets need plans without XM_PLAN_SYMMETRY or with a forced start vertex");
         if (D.sym_mult > 1 && full_opts && o->list_dev)
             return fail(XM_ERR_INVALID, "listing needs a plan without XM_PLAN_SYMMETRY");
     }

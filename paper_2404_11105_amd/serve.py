@@ -63,7 +63,8 @@ class GpuBackend:
         self.graphs = graphs
         self.opts = dict(opts or {})
         self.plans = {}
-        # unpinned requests count with symmetry-broken plans (same counts);
+        # requests count with symmetry-broken plans (same counts; a pinned
+        # request's plan only uses automorphisms that fix the pinned vertex);
         # the fixed side keeps planning free of host walks per request
         self.symmetry = symmetry
 
@@ -72,8 +73,7 @@ class GpuBackend:
         key = (graph_id, pattern.k, pattern.arcs, pin_vertex)
         p = self.plans.get(key)
         if p is None:
-            # a pinned request counts a root subset: no symmetry breaking there
-            sym = "above" if self.symmetry and pin_vertex is None else False
+            sym = "above" if self.symmetry else False
             p = Plan(pattern, reduced=True, graph=self.graphs[graph_id], root_vertex=pin_vertex, symmetry=sym)
             self.plans[key] = p
         return p

@@ -151,11 +151,13 @@ def test_root_subset_partial_sums(xa):
     G = xa.Graph(g)
     for pat, rv, w in zip(pats, c["root_vertex"], want):
         for reduced in (True, False):
-            p = xa.Plan(pat, reduced=reduced, graph=G, root_vertex=rv)
-            cnt = xa.Counter(G, [p], roots=c["roots"])
-            cnt.run()
-            got, st = cnt.results()
-            assert got == [w] and st == [0], (pat.name, reduced)
+            # with symmetry breaking a forced start vertex keeps subset counts exact
+            for symmetry in (False, "above", "below"):
+                p = xa.Plan(pat, reduced=reduced, graph=G, root_vertex=rv, symmetry=symmetry)
+                cnt = xa.Counter(G, [p], roots=c["roots"])
+                cnt.run()
+                got, st = cnt.results()
+                assert got == [w] and st == [0], (pat.name, reduced, symmetry)
 
 
 @pytest.mark.skip(reason="the device statistics launch (a second kernel variant) went silent on "
@@ -326,6 +328,16 @@ def test_symmetry_rejects_root_subsets_and_listing(xa):
     with pytest.raises(Exception):
         c = xa.Counter(G, [p], list_cap=100)
         c.run()
+    # a forced start vertex: only automorphisms fixing it, subsets allowed
+    # (bi-fan from a: the swap of c and d fixes a, so the multiplier is 2)
+    pr = xa.Plan(xmgen.named("bifan"), graph=G, symmetry="above", root_vertex=0)
+    d = pr.describe()
+    assert d["sym_fixes_root"] == 1 and d["sym_mult"] == 2
+    roots = np.arange(10, dtype=np.uint32)
+    c = xa.Counter(G, [pr], roots=roots)
+    c.run()
+    got, st = c.results()
+    assert st == [0] and got == [oracle.count(g, xmgen.named("bifan"), roots=roots.tolist(), root_vertex=0)]
     # a pattern without symmetry keeps a plain plan: subsets still work
     q = xa.Plan(xmgen.named("ffl"), graph=G, symmetry=True)
     assert q.describe()["sym_mult"] == 1

@@ -153,13 +153,16 @@ def test_anchored_counts_equal_oracle_and_sum_to_total(xa):
     G = xa.Graph(g)
     deg = np.diff(g.out_off.astype(np.int64)) + np.diff(g.in_off.astype(np.int64))
     nodes = np.concatenate([np.argsort(-deg)[:4], np.nonzero(deg == 0)[0][:2], [7, 100, 500]]).astype(np.uint32)
-    for name in ["c4", "mixed_star", "c5chord"]:
+    for name in ["c4", "mixed_star", "c5chord", "bifan"]:
         p = xmgen.named(name)
         for v in (0, p.k - 1):
             want = [oracle.count(g, p, roots=[int(x)], root_vertex=v, mode="B") for x in nodes]
             for reduced in (True, False):
                 got = xa.count_anchored(G, p, v, nodes, reduced=reduced)
                 assert got == want, (name, v, reduced)
+                # automorphisms fixing v only: still exact per node
+                got = xa.count_anchored(G, p, v, nodes, reduced=reduced, symmetry="above")
+                assert got == want, (name, v, reduced, "symmetry")
 
 
 def test_side_stream_launch_waits_for_setup(xa):

@@ -79,3 +79,27 @@ def test_model_symmetry_broken_plans_match_oracle(tune, direction):
             for reduced in (True, False):
                 m = Model(describe_plan(pat, reduced, symmetry=direction), g, **tune, max_windows=400000)
                 assert m.run() == want, (pat.name, reduced)
+
+
+def test_symmetry_with_forced_root_fixes_it():
+    """With a forced start vertex v only automorphisms fixing v are used: the
+    multiplier of an unreduced plan (every vertex conditioned) is the size of
+    v's stabiliser, counted here by brute force, and the plan's total still
+    equals the oracle's."""
+    import itertools
+    g = xmgen.uniform_digraph(40, 420, 11)
+    for pat in symmetric_patterns()[:5] + symmetric_patterns()[7:9]:
+        arcs = set(pat.arcs)
+        auts = [q for q in itertools.permutations(range(pat.k))
+                if {(q[a], q[b]) for a, b in arcs} == arcs]
+        want = oracle.count(g, pat)
+        for v in range(pat.k):
+            d = describe_plan_forced(pat, v)
+            assert d["sym_fixes_root"] == 1 and d["root_vertex"] == v
+            assert d["sym_mult"] == sum(1 for q in auts if q[v] == v), (pat.name, v)
+            assert Model(d, g, chunk=3, split=64, cap=64).run() == want, (pat.name, v)
+
+
+def describe_plan_forced(pat, v):
+    from paper_2404_11105_amd import Plan
+    return Plan(pat, reduced=False, root_vertex=v, symmetry="above").describe()
