@@ -122,6 +122,10 @@ def test_tiny_and_degenerate_graphs(xa):
         want = [oracle.count(g, p) for p in pats]
         assert run(xa, g, pats) == want, g.name
         assert run(xa, g, pats, reduced=False) == want, g.name
+        # the same with the graph in degree order and symmetry breaking
+        Gd = xa.Graph(g, order_by_degree=True)
+        assert run(xa, g, pats, G=Gd, symmetry=True) == want, g.name
+        assert run(xa, g, pats, G=Gd, reduced=False, symmetry="below") == want, g.name
 
 
 def test_complete_digraph_closed_form(xa):
