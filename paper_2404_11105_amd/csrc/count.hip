@@ -666,7 +666,6 @@ __device__ void leaf_masks(Ctx& C, uint32_t nb, uint32_t p, bool pv) {
     const uint32_t lane = C.lane;
     const uint32_t n_masks = uni(P->n_masks);
     for (uint32_t mi = 0; mi < n_masks; mi++) {
-        const uint32_t M = uni(P->mask_id[mi]);
         const LK K = load_lk(P->mdesc[mi], a);
         uint32_t h = 0;
         if (K.n_cons == 1 && K.reuse == kNoReuse) {
@@ -713,7 +712,9 @@ __device__ void leaf_masks(Ctx& C, uint32_t nb, uint32_t p, bool pv) {
                     if (((K.inj >> b) & 1u) && bound_in_set(C, ns, C.s.bound[b * 64 + lane])) h -= 1;
             wave_sync();
         }
-        C.s.hist[lane * 16 + M] = h;
+        // every mask whose test is this entry's takes its size
+        for (uint32_t ms = uni(P->mask_set[mi]) & 0xFFFEu; ms; ms &= ms - 1)
+            C.s.hist[lane * 16 + (uint32_t)__builtin_ctz(ms)] = h;
     }
     wave_sync();
     if (pv) {

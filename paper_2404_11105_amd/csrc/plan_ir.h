@@ -93,8 +93,11 @@ struct PlanDesc {
     // Every signature mask M used by a term block, with the candidate test of
     // the intersection of those signatures' sets (union of their constraints):
     // the kernel measures |intersection over s in M of S_s| per partial match.
+    // Masks whose tests coincide (the same union of constraints) share one
+    // entry: mask_set[i] holds every mask M (bit M) that takes entry i's size.
     uint32_t n_masks;
-    uint8_t mask_id[16];
+    uint8_t mask_id[16];          // first mask of entry i (reporting)
+    uint16_t mask_set[16];
     LevelDesc mdesc[kMaxMasks];
 };
 

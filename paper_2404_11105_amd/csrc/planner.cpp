@@ -582,8 +582,16 @@ std::string plan_json(const Pat& p, const PlanDesc& D, const CoverReport& cr, bo
         if (i) s += ",";
         std::string o = lvl_json(D.mdesc[i]);
         o.pop_back();
-        std::snprintf(buf, sizeof buf, ",\"mask\":%u}", D.mask_id[i]);
+        std::snprintf(buf, sizeof buf, ",\"mask\":%u,\"mask_set\":[", D.mask_id[i]);
         o += buf;
+        bool first = true;
+        for (uint32_t M = 1; M < 16; M++)
+            if ((D.mask_set[i] >> M) & 1u) {
+                std::snprintf(buf, sizeof buf, "%s%u", first ? "" : ",", M);
+                o += buf;
+                first = false;
+            }
+        o += "]}";
         s += o;
     }
     s += "],\"arcs\":[";
@@ -774,11 +782,21 @@ int build_plan(uint32_t k, uint32_t n_arcs, const uint8_t* arcs, uint32_t flags,
                     in |= sigs[g].in_mask;
                     out |= sigs[g].out_mask;
                 }
-            LevelDesc& L = D.mdesc[D.n_masks];
+            LevelDesc L;
+            std::memset(&L, 0, sizeof L);
             fill_level_sig(p, lvl_of, in, out, (int)D.e, L);
             // a node in every set of M has all of M's arcs to bound nodes
             if (reduced && D.e >= 2) choose_reuse(D, L, (int)D.e - 1, (uint32_t)popc(out), (uint32_t)popc(in));
-            D.mask_id[D.n_masks++] = (uint8_t)M;
+            // a mask whose test equals an earlier one's has the same set
+            uint32_t j = 0;
+            while (j < D.n_masks && std::memcmp(&D.mdesc[j], &L, sizeof L) != 0) j++;
+            if (j == D.n_masks) {
+                D.mdesc[j] = L;
+                D.mask_id[j] = (uint8_t)M;
+                D.mask_set[j] = 0;
+                D.n_masks++;
+            }
+            D.mask_set[j] |= (uint16_t)(1u << M);
         }
     }
     D.sym_mult = 1;

@@ -235,8 +235,9 @@ class Model:
                         j, d = M["cons"][0]
                         L = self.sets[d][bound[j]]
                         lo, hi = self._rng(bound[j], d)
-                        hist[M["mask"]] = (hi - lo) - sum(1 for b in range(lv + 1)
-                                                          if (M["inj"] >> b) & 1 and bound[b] in L)
+                        for mm in M["mask_set"]:
+                            hist[mm] = (hi - lo) - sum(1 for b in range(lv + 1)
+                                                       if (M["inj"] >> b) & 1 and bound[b] in L)
                         continue
                     m = self.phase_a(M, lv + 1, p, True, bound, anc)
                     cnt = 0
@@ -244,7 +245,8 @@ class Model:
                         x = self.base_elem(m, local, M["reuse"])
                         if self.check(M, lv + 1, bound, m, x):
                             cnt += 1
-                    hist[M["mask"]] = cnt
+                    for mm in M["mask_set"]:
+                        hist[mm] = cnt
                 val = 0
                 for t in P["terms"]:
                     prod = t["coef"]
