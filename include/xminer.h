@@ -115,8 +115,8 @@ int xm_graph_node_order(const xm_graph_t* g, uint32_t* new_of_old);
  * list length, at least max(min_len, 32), such that every out- and in-list
  * at least that long gets a row within max_bytes (the longest lists first).
  * *out_min_len (nullable) receives the threshold used, 0 if no row was
- * built.  max_bytes = 0 removes the rows; budgets above 16 GiB - 256 bytes
- * are treated as that.  Graphs with n >= 2^31 get no rows.  The call synchronises the device (launches in
+ * built.  max_bytes = 0 removes the rows; budgets above 256 GiB are treated
+ * as that.  Graphs with n >= 2^31 get no rows.  The call synchronises the device (launches in
  * flight may read the old rows) and fails with XM_ERR_INVALID while captured
  * launches (xm_exec_t) of this graph exist.  Rows cost ceil(n/32)*4 bytes
  * each; XM_ERR_OOM leaves the graph without rows. */
@@ -159,6 +159,15 @@ int xm_graph_info(const xm_graph_t* g, uint32_t* n, uint32_t* m,
  *                      keeps one image of v and root-subset counts stay
  *                      exact; without it xm_count refuses such a plan with a
  *                      root subset.  Listing refuses both;
+ *   XM_PLAN_ROOT_SHARE(s)  (s <= 31) count only the embeddings whose start
+ *                      vertex (xm_plan_root_vertex) maps to a node whose
+ *                      stored id r has r mod 2^s = 2^s - 1: an exact partial
+ *                      count over a fixed 1/2^s share of the roots, for
+ *                      patterns too heavy to count on every root (on a graph
+ *                      stored in degree order the share takes every 2^s-th
+ *                      node by degree rank, never the largest hub); with
+ *                      XM_PLAN_SYMMETRY only automorphisms that fix the
+ *                      start vertex are used, as with XM_PLAN_ROOT;
  *   XM_PLAN_SYM_BELOW  with XM_PLAN_SYMMETRY: keep per orbit the partial
  *                      match whose first conditioned vertex has the largest
  *                      image instead of the smallest (both exact; which
@@ -171,6 +180,7 @@ int xm_graph_info(const xm_graph_t* g, uint32_t* n, uint32_t* m,
 #define XM_PLAN_SYMMETRY 0x4u
 #define XM_PLAN_SYM_BELOW 0x8u
 #define XM_PLAN_ROOT(v) ((((uint32_t)(v)) + 1u) << 8)
+#define XM_PLAN_ROOT_SHARE(s) (((uint32_t)(s) & 0xFFu) << 16)
 int xm_plan(uint32_t k, uint32_t n_arcs, const uint8_t* arcs, uint32_t flags,
             const xm_graph_t* g, xm_plan_t** out);
 /* JSON description: vertex order, levels and their constraints, reuse
@@ -192,12 +202,39 @@ int xm_free_plan(xm_plan_t* p);
  * out[2] = partial matches of the enumerated levels, out[3] = roots that
  * pass the start vertex's degree constraint.  roots (nullable, host array)
  * limits the start vertex's images.  threads: host worker threads (0 = 1).
- * max_partial > 0 stops the walk once that many partial matches were seen;
- * the call then returns 1 (figures are partial sums) instead of XM_OK. */
+ * max_partial > 0 stops the walk once the partial matches seen plus the
+ * elements counted / 256 pass it; the call then returns 1 (figures are
+ * partial sums) instead of XM_OK. */
 int xm_plan_work(uint32_t n, const uint32_t* out_off, const uint32_t* out_adj,
                  const uint32_t* in_off, const uint32_t* in_adj, const xm_plan_t* p,
                  const uint32_t* roots, uint32_t n_roots, uint32_t threads,
                  uint64_t max_partial, uint64_t out[4]);
+
+/* Memory operations the count kernel issues for plan p on a graph given as
+ * HOST CSR arrays (same rules as xm_load_graph), for roofline accounting: a
+ * host computation that returns no count.  It walks the same partial matches
+ * as xm_plan_work (Algorithm 2's exploration with section 5.2's reuse and
+ * section 5.3's leaf counting) and counts, per partial match, what the
+ * kernel's candidate tests read as issued: the elements of each scanned
+ * base list, offset pairs, degree pairs, one word per membership test in a
+ * list of at least row_min elements (a dense row; 0 = no rows), the loads of
+ * a binary search otherwise (tests stop at the first failing list), and the
+ * partial matches written and their ancestor chains read back.  It assumes
+ * every window holds whole candidate sets (no hub sub-ranges or donated
+ * prefixes).  out[XM_TRAFFIC_WORDS]:
+ *   [0] base elements scanned (4 B each)     [1] offset pairs read (8 B)
+ *   [2] degree pairs read (8 B)               [3] dense-row words tested (4 B)
+ *   [4] sorted-list searches                  [5] words those searches load (4 B)
+ *   [6] partial matches written (8 B: node, parent)
+ *   [7] words of ancestor chains read back (4 B)
+ *   [8] roots passing the start vertex's degree filter
+ *   [9] adjacency elements intersected (merge model, as xm_plan_work out[0])
+ * roots, threads, max_partial and the return value as for xm_plan_work. */
+#define XM_TRAFFIC_WORDS 10
+int xm_plan_traffic(uint32_t n, const uint32_t* out_off, const uint32_t* out_adj,
+                    const uint32_t* in_off, const uint32_t* in_adj, const xm_plan_t* p,
+                    const uint32_t* roots, uint32_t n_roots, uint32_t row_min, uint32_t threads,
+                    uint64_t max_partial, uint64_t out[XM_TRAFFIC_WORDS]);
 
 /* ----------------------------------------------------------------------------
  * Counting (Algorithm 2; sections 5.2-5.3).

@@ -5,7 +5,7 @@ behind the C ABI of include/xminer.h.  This package only marshals
 arguments to it; PyTorch supplies device memory and streams.
 """
 from .api import (Graph, Plan, Counter, Watchdog, count, count_anchored, describe_plan, list_embeddings,
-                  plan_json, plan_work, workspace_bytes)
+                  plan_json, plan_traffic, plan_work, workspace_bytes)
 
 __all__ = ["Graph", "Plan", "Counter", "Watchdog", "count", "count_anchored", "describe_plan",
-           "list_embeddings", "plan_json", "plan_work", "workspace_bytes"]
+           "list_embeddings", "plan_json", "plan_traffic", "plan_work", "workspace_bytes"]

@@ -36,6 +36,10 @@ def XM_PLAN_ROOT(v: int) -> int:
     return (v + 1) << 8
 
 
+def XM_PLAN_ROOT_SHARE(s: int) -> int:
+    return (int(s) & 0xFF) << 16
+
+
 class XmCountOpts(ctypes.Structure):
     _fields_ = [
         ("struct_size", ctypes.c_uint32),
@@ -69,7 +73,7 @@ class XminerError(RuntimeError):
 EXPORTS = [
     "xm_load_graph", "xm_free_graph", "xm_graph_info", "xm_graph_node_order", "xm_graph_dense_rows", "xm_graph_dense_rows_info",
     "xm_plan", "xm_plan_describe",
-    "xm_plan_root_vertex", "xm_free_plan", "xm_plan_work", "xm_workspace_size", "xm_count", "xm_count_capture",
+    "xm_plan_root_vertex", "xm_free_plan", "xm_plan_work", "xm_plan_traffic", "xm_workspace_size", "xm_count", "xm_count_capture",
     "xm_exec_launch", "xm_free_exec", "xm_strerror", "xm_last_error", "xm_version",
 ]
 
@@ -96,6 +100,7 @@ def lib():
         L.xm_plan_root_vertex.argtypes = [P]
         L.xm_free_plan.argtypes = [P]
         L.xm_plan_work.argtypes = [U32, P, P, P, P, P, P, U32, U32, ctypes.c_uint64, P]
+        L.xm_plan_traffic.argtypes = [U32, P, P, P, P, P, P, U32, U32, U32, ctypes.c_uint64, P]
         L.xm_workspace_size.argtypes = [P, U32, P, P]
         L.xm_workspace_size.restype = SZ
         L.xm_count.argtypes = [P, U32, P, P, P, SZ, P, P, P]
@@ -109,7 +114,7 @@ def lib():
         for name in ["xm_load_graph", "xm_free_graph", "xm_graph_info", "xm_graph_dense_rows",
                      "xm_graph_dense_rows_info", "xm_plan",
                      "xm_plan_describe", "xm_plan_root_vertex", "xm_free_plan", "xm_plan_work",
-                     "xm_count",
+                     "xm_plan_traffic", "xm_count",
                      "xm_count_capture", "xm_exec_launch", "xm_free_exec"]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L

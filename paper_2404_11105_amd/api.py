@@ -163,14 +163,20 @@ class Plan:
     that vertex are used).  "above" keeps, per orbit, the embedding whose first
     conditioned vertex has the smallest image; "below" the largest; True picks
     the one with less estimated work on `graph` (a sampled host walk), or
-    "above" without a host copy of the graph."""
+    "above" without a host copy of the graph.
+
+    root_share = s > 0 counts only the embeddings whose start vertex maps to
+    a node with stored id r, r mod 2^s = 2^s - 1: an exact partial count over
+    a fixed share of the roots (with symmetry, only automorphisms that fix
+    the start vertex are used)."""
 
     def __init__(self, pattern, reduced: bool = True, graph: Graph | None = None,
-                 root_vertex: int | None = None, symmetry=False):
+                 root_vertex: int | None = None, symmetry=False, root_share: int = 0):
         self.pattern = pattern
         self.reduced = reduced
+        self.root_share = int(root_share)
         if symmetry is True:
-            symmetry = _choose_direction(pattern, reduced, graph, root_vertex)
+            symmetry = _choose_direction(pattern, reduced, graph, root_vertex, root_share)
         if symmetry not in (False, "above", "below"):
             raise ValueError("symmetry must be False, True, 'above' or 'below'")
         self.symmetry = symmetry
@@ -182,6 +188,8 @@ class Plan:
             flags |= _lib.XM_PLAN_SYM_BELOW
         if root_vertex is not None:
             flags |= _lib.XM_PLAN_ROOT(root_vertex)
+        if root_share:
+            flags |= _lib.XM_PLAN_ROOT_SHARE(root_share)
         h = ctypes.c_void_p()
         check(lib().xm_plan(pattern.k, len(pattern.arcs), arcs, flags,
                             graph.handle if graph is not None else None, ctypes.byref(h)))
@@ -214,8 +222,8 @@ def plan_json(plan: Plan) -> str:
     return buf.value.decode()
 
 
-def describe_plan(pattern, reduced: bool = True, symmetry=False) -> dict:
-    return Plan(pattern, reduced, symmetry=symmetry).describe()
+def describe_plan(pattern, reduced: bool = True, symmetry=False, root_share: int = 0) -> dict:
+    return Plan(pattern, reduced, symmetry=symmetry, root_share=root_share).describe()
 
 
 SYM_FETCH_COST = 64      # one list fetch weighs as much as this many elements
@@ -224,7 +232,7 @@ SYM_SAMPLE_REST = 4096   # other nodes, strided
 SYM_WALK_CAP = 200_000_000  # partial matches per estimate
 
 
-def _choose_direction(pattern, reduced, graph, root_vertex):
+def _choose_direction(pattern, reduced, graph, root_vertex, root_share=0):
     """The symmetry direction with the smaller estimated work: the host walk
     (elements + SYM_FETCH_COST x list fetches) over the hub roots and a
     strided sample of the others, scaled to all roots.  Patterns without
@@ -233,7 +241,8 @@ def _choose_direction(pattern, reduced, graph, root_vertex):
     if graph is None or getattr(graph, "host", None) is None:
         return "above"
     g = graph.host
-    cand = {d: Plan(pattern, reduced, root_vertex=root_vertex, symmetry=d) for d in ("above", "below")}
+    cand = {d: Plan(pattern, reduced, root_vertex=root_vertex, symmetry=d, root_share=root_share)
+            for d in ("above", "below")}
     if cand["above"].describe()["sym_mult"] == 1:
         return "above"
     deg = np.diff(np.asarray(g.out_off, dtype=np.int64)) + np.diff(np.asarray(g.in_off, dtype=np.int64))
@@ -437,6 +446,41 @@ def plan_work(digraph, plan: Plan, roots=None, threads: int = 1, max_partial: in
                                   ptr(r) if r is not None else None, nr, threads, max_partial, out))
     return dict(elements=out[0], fetches=out[1], partial_matches=out[2], roots=out[3],
                 exceeded=rc == 1)
+
+
+TRAFFIC_KEYS = ("base_elements", "offset_pairs", "degree_pairs", "row_words", "searches", "search_words",
+                "partial_matches", "chain_words", "roots", "elements_merge")
+
+
+def plan_traffic(digraph, plan: Plan, row_min: int = 0, roots=None, threads: int = 1,
+                 max_partial: int = 0) -> dict:
+    """Memory operations the count kernel issues for `plan` on a host graph
+    (xm_plan_traffic; statistics only, no count).  row_min: the graph's dense
+    row threshold (0: no rows).  The dict also holds `bytes`: 4 B per base
+    element, row word, search word and chain word, 8 B per offset pair,
+    degree pair and partial match written."""
+    arrs = [np.ascontiguousarray(a, dtype=np.uint32) for a in
+            (digraph.out_off, digraph.out_adj, digraph.in_off, digraph.in_adj)]
+    arrs = [a if a.size else np.zeros(1, dtype=np.uint32) for a in arrs]
+    out = (ctypes.c_uint64 * len(TRAFFIC_KEYS))()
+    r, nr = None, 0
+    if roots is not None:
+        r = np.ascontiguousarray(roots, dtype=np.uint32)
+        nr = int(r.size)
+    ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    rc = check(lib().xm_plan_traffic(int(digraph.n), *[ptr(a) for a in arrs], plan.handle,
+                                     ptr(r) if r is not None else None, nr, int(row_min), threads,
+                                     max_partial, out))
+    d = {k: int(v) for k, v in zip(TRAFFIC_KEYS, out)}
+    d["bytes"] = traffic_bytes(d)
+    d["exceeded"] = rc == 1
+    return d
+
+
+def traffic_bytes(d: dict) -> int:
+    """Bytes of the issued model: what the kernel's tests read and write."""
+    return (4 * (d["base_elements"] + d["row_words"] + d["search_words"] + d["chain_words"])
+            + 8 * (d["offset_pairs"] + d["degree_pairs"] + d["partial_matches"]))
 
 
 class Watchdog:

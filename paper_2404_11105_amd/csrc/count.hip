@@ -28,6 +28,7 @@
 #include <stdint.h>
 
 #include "kernels.h"
+#include "u128.h"
 
 namespace xm {
 
@@ -149,7 +150,7 @@ __device__ __forceinline__ LK load_lk(const LevelDesc& D, const KArgs& a) {
     return k;
 }
 
-// Unsigned 128-bit add into (lo, hi) with an overflow flag.
+// Unsigned 128-bit atomic add into (lo, hi) with an overflow flag.
 __device__ void add_u128(unsigned long long* c, unsigned long long lo, unsigned long long hi,
                          uint32_t* flag) {
     if (lo) {
@@ -227,6 +228,7 @@ struct Ctx {
     uint32_t* scr;
     uint32_t lane;
     unsigned long long acc_lo, acc_hi;  // per-lane 128-bit partial (leaf groups)
+    bool ovf;                           // this lane's partial or a leaf-group term left the 128-bit range
     bool donated;                       // this wave has handed off work (it then always waits)
 };
 
@@ -447,9 +449,11 @@ __device__ __forceinline__ void check_pair(const Ctx& C, const LK& D, uint32_t i
             okb = okb && (xb != C.s.bound[l * 64 + jb]);
         }
     if (D.deg_check) {
-        const uint2 da = g.deg[oka ? xa : 0u], db = g.deg[okb ? xb : 0u];
-        oka = oka && da.x >= D.dmin_out && da.y >= D.dmin_in;
-        okb = okb && db.x >= D.dmin_out && db.y >= D.dmin_in;
+        // one byte per node: in degree order the frequent candidates (hubs)
+        // share a few cache lines
+        const uint32_t da = g.degc[oka ? xa : 0u], db = g.degc[okb ? xb : 0u];
+        oka = oka && (da & 15u) >= D.dmin_out && (da >> 4) >= D.dmin_in;
+        okb = okb && (db & 15u) >= D.dmin_out && (db >> 4) >= D.dmin_in;
     }
     const uint32_t* safe = safe_ptr(g);
     for (uint32_t k = 0; k < ns; k++) {
@@ -718,21 +722,23 @@ __device__ void leaf_masks(Ctx& C, uint32_t nb, uint32_t p, bool pv) {
     }
     wave_sync();
     if (pv) {
-        // inclusion-exclusion over set partitions of the leaves
+        // inclusion-exclusion over set partitions of the leaves; a term whose
+        // magnitude could pass 2^120 marks the plan as overflowed
         const uint32_t* h = C.s.hist + lane * 16;
         __int128 val = 0;
+        bool big = false;
         const uint32_t n_terms = uni(P->n_terms);
         for (uint32_t t = 0; t < n_terms; t++) {
             const Term& tm = P->terms[t];
-            __int128 prod = tm.coef;
-            for (uint32_t b = 0; b < tm.nb; b++) prod *= (__int128)h[tm.mask[b]];
-            val += prod;
+            uint32_t hv[kMaxBlocks];
+            const uint32_t nb = tm.nb < kMaxBlocks ? tm.nb : kMaxBlocks;
+            for (uint32_t b = 0; b < nb; b++) hv[b] = h[tm.mask[b] & 15u];
+            val += ie_term(tm.coef, hv, nb, &big);
         }
-        unsigned __int128 v = (unsigned __int128)val;
-        unsigned long long vl = (unsigned long long)v, vh = (unsigned long long)(v >> 64);
-        unsigned long long o = C.acc_lo;
-        C.acc_lo += vl;
-        C.acc_hi += vh + (C.acc_lo < o ? 1ull : 0ull);
+        // the injective count of one partial match is never negative
+        const unsigned __int128 v = (unsigned __int128)(val < 0 ? (__int128)0 : val);
+        if (big || val < 0) C.ovf = true;
+        if (u128_add(C.acc_lo, C.acc_hi, (unsigned long long)v, (unsigned long long)(v >> 64))) C.ovf = true;
     }
     wave_sync();
 }
@@ -804,9 +810,7 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
                 for (uint32_t b = 0; b < nb; b++)
                     if (((S0.inj >> b) & 1u) && contains(L, l, C.s.bound[b * 64 + lane])) v -= 1;
             }
-            unsigned long long o = C.acc_lo;
-            C.acc_lo += v;
-            if (C.acc_lo < o) C.acc_hi += 1;
+            if (u128_add(C.acc_lo, C.acc_hi, v, 0ull)) C.ovf = true;
             wave_sync();
             continue;
         }
@@ -884,29 +888,27 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
                 lin += merge_count(C.s, A, blen, B, plen, S.inj, nb, j, lane);
             }
         }
-        if (lane == 0) {
-            unsigned long long o = C.acc_lo;
-            C.acc_lo += lin;
-            if (C.acc_lo < o) C.acc_hi += 1;
-        }
+        if (lane == 0 && u128_add(C.acc_lo, C.acc_hi, lin, 0ull)) C.ovf = true;
         wave_sync();
     }
 }
 
 __device__ void flush(Ctx& C) {
     unsigned long long lo = C.acc_lo, hi = C.acc_hi;
+    bool ovf = C.ovf;
     // wave reduction of 128-bit partials
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
         unsigned long long olo = __shfl_xor(lo, d, 64);
         unsigned long long ohi = __shfl_xor(hi, d, 64);
-        unsigned long long nlo = lo + olo;
-        hi = hi + ohi + (nlo < lo ? 1ull : 0ull);
-        lo = nlo;
+        if (u128_add(lo, hi, olo, ohi)) ovf = true;
     }
+    const bool any_ovf = __ballot(ovf) != 0;
     if (C.lane == 0 && (lo | hi))
         add_u128(C.a->counts + 2 * C.pi, lo, hi, C.a->plan_flags + C.pi);
+    if (C.lane == 0 && any_ovf) atomicOr(C.a->plan_flags + C.pi, 1u);
     C.acc_lo = C.acc_hi = 0;
+    C.ovf = false;
 }
 
 // Work donation.  While some waves are idle (all queues drained), a wave that
@@ -1031,6 +1033,7 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
     const uint64_t gw = (uint64_t)blockIdx.x * kWavesPerBlock + wid;
     C.scr = a.scratch + gw * (uint64_t)a.wave_words;
     C.acc_lo = C.acc_hi = 0;
+    C.ovf = false;
     C.pi = 0;
     C.P = a.plans;
     C.donated = false;
@@ -1038,8 +1041,9 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
     // the 8 XCDs round-robin), so a hub's sub-range tasks share one L2
     const uint32_t home = blockIdx.x % kQueues;
     bool split_left = true;
-    const uint32_t chunks_per_plan = (a.n_src + a.chunk - 1) / a.chunk;
-    const uint32_t total_chunks = chunks_per_plan * a.n_plans;
+    // 64-bit: the host keeps the product below 2^32 (root items are 32-bit)
+    const uint64_t chunks_per_plan = ((uint64_t)a.n_src + a.chunk - 1) / a.chunk;
+    const uint64_t total_chunks = chunks_per_plan * a.n_plans;
     Lvl F0 = lvl_arrays(C.scr, a.cap, 0);
     uint32_t taken = 0;
     // root items come from kQueues interleaved cursors (cursor q: items q,
@@ -1190,7 +1194,7 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
             uint32_t r = 0;
             if (ok) {
                 r = a.roots ? a.roots[idx] : idx;
-                ok = r < a.g.n;
+                ok = r < a.g.n && in_root_share(r, C.P->root_share);
             }
             if (ok) {
                 uint2 d = a.g.deg[r];
@@ -1228,7 +1232,7 @@ __global__ void split_kernel(KArgs a) {
         const PlanDesc* P = a.plans + pi;
         if (P->e < 2) continue;
         uint32_t r = a.roots ? a.roots[h] : a.hubs[h];
-        if (r >= a.g.n) continue;
+        if (r >= a.g.n || !in_root_share(r, P->root_share)) continue;
         uint2 d = a.g.deg[r];
         if (d.x < P->root_dout || d.y < P->root_din) continue;
         uint32_t len = level1_len(a.g, P, r);
@@ -1284,11 +1288,10 @@ __global__ void finalize_kernel(KArgs a) {
         if (m > 1 && st == 0) {
             // one embedding per orbit was counted: scale the 128-bit total
             unsigned long long* c = a.counts + 2 * i;
-            const unsigned __int128 lo = (unsigned __int128)c[0] * m;
-            const unsigned __int128 hi = (unsigned __int128)c[1] * m + (unsigned long long)(lo >> 64);
-            if (hi >> 64) st = -5;
-            c[0] = (unsigned long long)lo;
-            c[1] = (unsigned long long)hi;
+            unsigned long long lo = c[0], hi = c[1];
+            if (u128_scale(lo, hi, m)) st = -5;
+            c[0] = lo;
+            c[1] = hi;
         }
         a.status[i] = st;
     }

@@ -42,11 +42,12 @@ struct DevGraph {
     const uint32_t* in_off;
     const uint32_t* in_adj;
     const uint2* deg;   // (out-degree, in-degree)
+    const uint8_t* degc;  // min(out-degree, 15) | min(in-degree, 15) << 4
     uint32_t n;
     uint32_t row_min;   // lists at least this long have a dense row (kNoRows: none)
     // dense membership rows of long lists: row r is row_words uint32 words at
-    // word offset r * row_words (out rows first, then in rows; < 16 GiB in
-    // all, so word offsets fit 32 bits), bit x set iff node x is in the list
+    // word offset r * row_words, computed in 64 bits (out rows first, then in
+    // rows), bit x set iff node x is in the list
     const uint32_t* rows;
     const uint2* row_of;  // per node: (out row, in row), 0xFFFFFFFF = no row
     uint32_t row_words;
@@ -56,7 +57,7 @@ struct DevGraph {
 constexpr uint32_t kNoRows = 0xFFFFFFFFu;
 constexpr uint32_t kRowLen = 0xFFFFFFFEu;  // probe-list length marker: test a dense row
 
-constexpr uint64_t kMaxRowBytes = (16ull << 30) - 256;  // rows are addressed by 32-bit word offsets
+constexpr uint64_t kMaxRowBytes = 256ull << 30;  // rows budget, at most (row ids are 32-bit)
 
 // Set the bits of dense rows [0, n_rows): row r holds the out-list (r <
 // n_out_rows) or in-list of node row_node[r].  Rows must be zeroed first.
@@ -140,6 +141,14 @@ __host__ __device__ inline uint32_t plan_item_size(uint32_t L1, uint32_t e, uint
     return item_size(L1, split, split_work);
 }
 
+// Whether root r belongs to a plan's root share s: r mod 2^s = 2^s - 1
+// (every root when s = 0).  The residue 2^s - 1 keeps node 0 -- on a graph
+// stored in degree order, the largest hub -- out of every proper share.
+__host__ __device__ inline bool in_root_share(uint32_t r, uint32_t s) {
+    const uint32_t mask = s >= 32 ? 0xFFFFFFFFu : ((1u << s) - 1u);
+    return ((r + 1u) & mask) == 0u;
+}
+
 // LDS words per wave: `rows` bound levels (the largest enumerated depth of
 // the batch), the largest constraint count, and the optional parts.
 inline uint32_t lds_words_for(uint32_t rows, uint32_t maxc, bool nonlinear, bool merge) {
@@ -164,11 +173,20 @@ struct HostCsr {
     uint32_t n;
 };
 struct WorkOut {
+    // merge model: every element of every list a partial match intersects
     uint64_t elements = 0, fetches = 0, partial = 0, roots = 0;
+    // what the count kernel reads and writes per partial match (its
+    // candidate tests as issued: base elements scanned, offset pairs,
+    // degree pairs, dense-row words, sorted-list searches and the words
+    // they read, partial matches written and the chains read back)
+    uint64_t base = 0, offset_pairs = 0, deg_reads = 0, row_probes = 0, searches = 0, search_words = 0,
+             chain_words = 0;
 };
 // Returns true when the walk stopped early because it passed max_partial
 // partial matches (0 = no limit); the figures are then partial sums.
+// row_min: lists at least this long are tested through dense rows
+// (kNoRows: none).
 bool plan_work(const HostCsr& g, const PlanDesc& p, const uint32_t* roots, uint32_t n_roots,
-               unsigned threads, uint64_t max_partial, WorkOut& out);
+               unsigned threads, uint64_t max_partial, uint32_t row_min, WorkOut& out);
 
 }  // namespace xm

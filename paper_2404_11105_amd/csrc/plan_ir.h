@@ -88,7 +88,8 @@ struct PlanDesc {
     uint8_t sig_mult[kMaxSig];    // leaves per signature
     uint8_t order[kMaxK];         // level -> pattern vertex (reporting)
     uint8_t sym_fixes_root;       // 1: the symmetry group fixes the start vertex (root subsets stay exact)
-    uint8_t pad2[4];
+    uint8_t root_share;           // s: only roots (stored ids) r with r mod 2^s = 2^s - 1 are tried (0: all)
+    uint8_t pad2[3];
     Term terms[kMaxTerms];
     // Every signature mask M used by a term block, with the candidate test of
     // the intersection of those signatures' sets (union of their constraints):

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -516,11 +517,218 @@ void apply_symmetry(const Pat& p, PlanDesc& D, bool below, bool fix_root) {
     for (uint32_t i = 0; i < D.n_masks; i++) fix_reuse(D.mdesc[i]);
 }
 
+// ---------------------------------------------------------------------------
+// Plan candidates and their realized constraint covers
+// ---------------------------------------------------------------------------
+struct Built {
+    PlanDesc D;
+    std::vector<int> order, leaves, leaf_sig;  // leaf_sig[i]: signature index of leaves[i]
+    double cost = 0, cover_w = 0;
+};
+
+// Every order of the enumerated vertices E that starts at `start` and binds
+// each next vertex next to an already bound one (section 5.1: the plan
+// extends from the visited vertices).
+std::vector<std::vector<int>> enum_orders(const Pat& p, int start, uint32_t emask) {
+    std::vector<std::vector<int>> out;
+    std::vector<int> cur{start};
+    const int want = popc(emask);
+    std::function<void(uint32_t)> rec = [&](uint32_t bound) {
+        if ((int)cur.size() == want) {
+            out.push_back(cur);
+            return;
+        }
+        for (int v = 0; v < p.k; v++) {
+            if (!(emask & (1u << v)) || (bound & (1u << v))) continue;
+            if (!(p.nbr(v) & bound)) continue;
+            cur.push_back(v);
+            rec(bound | (1u << v));
+            cur.pop_back();
+        }
+    };
+    rec(1u << start);
+    return out;
+}
+
+// Levels, leaf signatures, inclusion-exclusion terms and per-mask tests of
+// the plan with this vertex order and leaf group.  Returns false when the
+// leaf group needs more terms than the descriptor holds.
+bool build_desc(const Pat& p, const std::vector<int>& order, const std::vector<int>& leaves, bool reduced, Built& B) {
+    PlanDesc& D = B.D;
+    std::memset(&D, 0, sizeof(D));
+    B.order = order;
+    B.leaves = leaves;
+    B.leaf_sig.clear();
+    D.k = (uint32_t)p.k;
+    D.e = (uint32_t)order.size();
+    std::vector<int> lvl_of(p.k, -1);
+    for (size_t i = 0; i < order.size(); i++) lvl_of[order[i]] = (int)i;
+    for (size_t i = 0; i < order.size(); i++) D.order[i] = (uint8_t)order[i];
+    D.root_dout = (uint32_t)p.dout(order[0]);
+    D.root_din = (uint32_t)p.din(order[0]);
+    uint32_t leaf_mask = 0;
+    for (int v : leaves) leaf_mask |= 1u << v;
+    for (uint32_t i = 1; i < D.e; i++) {
+        int v = order[i];
+        uint32_t later = leaf_mask;
+        for (size_t j = i + 1; j < order.size(); j++) later |= 1u << order[j];
+        fill_level(p, lvl_of, v, (int)i, later, D.lvl[i]);
+        if (reduced && i >= 2) choose_reuse(D, D.lvl[i], (int)i - 1, D.lvl[i].dmin_out, D.lvl[i].dmin_in);
+    }
+    // leaf signatures
+    std::vector<LeafSig> sigs;
+    for (int v : leaves) {
+        LeafSig s{p.in[v], p.out[v]};
+        if (std::find(sigs.begin(), sigs.end(), s) == sigs.end()) sigs.push_back(s);
+    }
+    std::sort(sigs.begin(), sigs.end());
+    D.n_sig = (uint32_t)sigs.size();
+    D.t = (uint32_t)leaves.size();
+    for (int v : leaves) {
+        LeafSig s{p.in[v], p.out[v]};
+        int g = (int)(std::find(sigs.begin(), sigs.end(), s) - sigs.begin());
+        B.leaf_sig.push_back(g);
+        D.sig_mult[g]++;
+    }
+    for (uint32_t g = 0; g < D.n_sig; g++) {
+        // any leaf of this signature gives the same constraint set
+        int v = -1;
+        for (size_t i = 0; i < leaves.size(); i++)
+            if (B.leaf_sig[i] == (int)g) v = leaves[i];
+        fill_level(p, lvl_of, v, (int)D.e, 0u, D.sig[g]);
+        D.sig[g].dmin_out = D.sig[g].dmin_in = 0;  // implied by the constraints of a leaf
+        D.sig[g].deg_check = 0;
+        if (reduced && D.e >= 2)
+            choose_reuse(D, D.sig[g], (int)D.e - 1, (uint32_t)p.dout(v), (uint32_t)p.din(v));
+    }
+    std::vector<Term> terms;
+    if (!leaf_terms(B.leaf_sig, terms)) return false;
+    D.n_terms = (uint32_t)terms.size();
+    for (size_t i = 0; i < terms.size(); i++) D.terms[i] = terms[i];
+    D.linear = (D.t == 1) ? 1 : 0;
+    for (size_t i = 0; i < leaves.size(); i++) D.order[D.e + i] = (uint8_t)leaves[i];
+    // one candidate test per signature mask the terms use
+    uint32_t used = 0;
+    for (uint32_t i = 0; i < D.n_terms; i++)
+        for (int b = 0; b < D.terms[i].nb; b++) used |= 1u << D.terms[i].mask[b];
+    D.n_masks = 0;
+    for (uint32_t M = 1; M < 16; M++) {
+        if (!((used >> M) & 1u)) continue;
+        uint32_t in = 0, out = 0;
+        for (uint32_t g = 0; g < D.n_sig; g++)
+            if ((M >> g) & 1u) {
+                in |= sigs[g].in_mask;
+                out |= sigs[g].out_mask;
+            }
+        LevelDesc L;
+        std::memset(&L, 0, sizeof L);
+        fill_level_sig(p, lvl_of, in, out, (int)D.e, L);
+        // a node in every set of M has all of M's arcs to bound nodes
+        if (reduced && D.e >= 2) choose_reuse(D, L, (int)D.e - 1, (uint32_t)popc(out), (uint32_t)popc(in));
+        // a mask whose test equals an earlier one's has the same set
+        uint32_t j = 0;
+        while (j < D.n_masks && std::memcmp(&D.mdesc[j], &L, sizeof L) != 0) j++;
+        if (j == D.n_masks) {
+            D.mdesc[j] = L;
+            D.mask_id[j] = (uint8_t)M;
+            D.mask_set[j] = 0;
+            D.n_masks++;
+        }
+        D.mask_set[j] |= (uint16_t)(1u << M);
+    }
+    return true;
+}
+
+// The arcs the plan reads from the data graph (its realized constraint
+// cover).  A level fetches every constraint list it does not take from a
+// reused candidate set (section 5.2: an included arc is materialised from
+// the including arc's result); the leaf passes the kernel runs (the one
+// signature of a one-leaf plan, else every signature mask) fetch the same
+// way, and a list read for several leaves of one signature is attributed to
+// the first of them, the other leaves' arcs being included by its arc
+// (shared endpoint, Theorem 2.1).  Bit i stands for p.arcs[i].
+uint64_t fetched_arcs(const Pat& p, const Built& B) {
+    const PlanDesc& D = B.D;
+    auto arc_index = [&](int a, int b) -> int {
+        for (size_t i = 0; i < p.arcs.size(); i++)
+            if (p.arcs[i].first == a && p.arcs[i].second == b) return (int)i;
+        return -1;
+    };
+    uint64_t f = 0;
+    // dir 0: x in out(phi(u)), arc u -> x; dir 1: x in in(phi(u)), arc x -> u
+    auto mark = [&](int u, int x, int dir) {
+        const int i = dir ? arc_index(x, u) : arc_index(u, x);
+        if (i >= 0) f |= 1ull << i;
+    };
+    auto read = [&](const LevelDesc& L, int c) { return L.reuse == kNoReuse || ((L.extra >> c) & 1u); };
+    for (uint32_t i = 1; i < D.e; i++) {
+        const LevelDesc& L = D.lvl[i];
+        for (int c = 0; c < L.n_cons; c++)
+            if (read(L, c)) mark(B.order[L.cons_lvl[c]], B.order[i], L.cons_dir[c]);
+    }
+    auto rep = [&](uint32_t g) {
+        for (size_t i = 0; i < B.leaves.size(); i++)
+            if (B.leaf_sig[i] == (int)g) return B.leaves[i];
+        return -1;
+    };
+    auto has_cons = [](const LevelDesc& L, int lvl, int dir) {
+        for (int c = 0; c < L.n_cons; c++)
+            if (L.cons_lvl[c] == lvl && L.cons_dir[c] == dir) return true;
+        return false;
+    };
+    if (D.linear) {
+        const LevelDesc& L = D.sig[0];
+        for (int c = 0; c < L.n_cons; c++)
+            if (read(L, c)) mark(B.order[L.cons_lvl[c]], rep(0), L.cons_dir[c]);
+    } else {
+        for (uint32_t mi = 0; mi < D.n_masks; mi++) {
+            const LevelDesc& L = D.mdesc[mi];
+            const uint32_t M = D.mask_id[mi];
+            for (int c = 0; c < L.n_cons; c++) {
+                if (!read(L, c)) continue;
+                for (uint32_t g = 0; g < D.n_sig; g++)
+                    if (((M >> g) & 1u) && has_cons(D.sig[g], L.cons_lvl[c], L.cons_dir[c])) {
+                        mark(B.order[L.cons_lvl[c]], rep(g), L.cons_dir[c]);
+                        break;
+                    }
+            }
+        }
+    }
+    return f;
+}
+
+// Weight of the realized cover: for every list read, the estimated number of
+// partial matches that read it times the mean list length (unit graph of
+// 10^6 nodes and mean degree 16 without statistics).  Partial matches grow
+// by d (d/n)^(c-1) per level with c constraints.
+double cover_weight(const Pat& p, const Built& B, const GraphStats* gs) {
+    const PlanDesc& D = B.D;
+    const double n = (gs && gs->n) ? (double)gs->n : 1e6;
+    const double d = (gs && gs->n) ? std::max(1.0, (double)gs->m / (double)gs->n) : 16.0;
+    double P[kMaxK + 1];
+    P[0] = n;
+    for (uint32_t i = 1; i < D.e; i++) P[i] = P[i - 1] * d * std::pow(d / n, (double)D.lvl[i].n_cons - 1.0);
+    auto reads = [](const LevelDesc& L) {
+        int r = 0;
+        for (int c = 0; c < L.n_cons; c++) r += (L.reuse == kNoReuse || ((L.extra >> c) & 1u)) ? 1 : 0;
+        return r;
+    };
+    double w = 0;
+    for (uint32_t i = 1; i < D.e; i++) w += P[i - 1] * d * reads(D.lvl[i]);
+    if (D.linear) {
+        w += P[D.e - 1] * d * reads(D.sig[0]);
+    } else {
+        for (uint32_t mi = 0; mi < D.n_masks; mi++) w += P[D.e - 1] * d * reads(D.mdesc[mi]);
+    }
+    (void)p;
+    return w;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 std::string plan_json(const Pat& p, const PlanDesc& D, const CoverReport& cr, bool reduced,
-                      double cost) {
+                      double cost, uint64_t fetched, double cover_w) {
     std::string s;
     char buf[256];
     auto arcstr = [&](int e) {
@@ -565,8 +773,11 @@ std::string plan_json(const Pat& p, const PlanDesc& D, const CoverReport& cr, bo
         o += buf;
         s += o;
     }
-    std::snprintf(buf, sizeof buf, "],\"t\":%u,\"linear\":%u,\"seg_src\":%u,\"sym_mult\":%u,\"sym_fixes_root\":%u,\"terms\":[",
-                  D.t, D.linear, D.seg_src, D.sym_mult ? D.sym_mult : 1u, (unsigned)D.sym_fixes_root);
+    std::snprintf(buf, sizeof buf,
+                  "],\"t\":%u,\"linear\":%u,\"seg_src\":%u,\"sym_mult\":%u,\"sym_fixes_root\":%u,\"root_share\":%u,"
+                  "\"terms\":[",
+                  D.t, D.linear, D.seg_src, D.sym_mult ? D.sym_mult : 1u, (unsigned)D.sym_fixes_root,
+                  (unsigned)D.root_share);
     s += buf;
     for (uint32_t i = 0; i < D.n_terms; i++) {
         std::snprintf(buf, sizeof buf, "%s{\"coef\":%d,\"masks\":[", i ? "," : "", D.terms[i].coef);
@@ -611,7 +822,25 @@ std::string plan_json(const Pat& p, const PlanDesc& D, const CoverReport& cr, bo
     std::snprintf(buf, sizeof buf, "],\"min_cover_weight\":%.6g,\"greedy_cover\":[", cr.min_cover_weight);
     s += buf;
     for (size_t i = 0; i < cr.greedy_cover.size(); i++) s += (i ? "," : "") + arcstr(cr.greedy_cover[i]);
-    std::snprintf(buf, sizeof buf, "],\"removed_edges\":%zu}", p.arcs.size() - cr.min_cover.size());
+    // the plan's realized cover: arcs read from the data graph, and arcs whose
+    // candidates come from an including arc's result
+    s += "],\"cover\":{\"fetched\":[";
+    bool first = true;
+    for (size_t e = 0; e < p.arcs.size(); e++)
+        if ((fetched >> e) & 1ull) {
+            s += (first ? "" : ",") + arcstr((int)e);
+            first = false;
+        }
+    s += "],\"removed\":[";
+    first = true;
+    size_t removed = 0;
+    for (size_t e = 0; e < p.arcs.size(); e++)
+        if (!((fetched >> e) & 1ull)) {
+            s += (first ? "" : ",") + arcstr((int)e);
+            first = false;
+            removed++;
+        }
+    std::snprintf(buf, sizeof buf, "],\"weight\":%.6g},\"removed_edges\":%zu}", cover_w, removed);
     s += buf;
     return s;
 }
@@ -655,6 +884,11 @@ int build_plan(uint32_t k, uint32_t n_arcs, const uint8_t* arcs, uint32_t flags,
         return -1;
     }
     int forced = (int)((flags >> 8) & 0xFu) - 1;
+    const uint32_t share = (flags >> 16) & 0xFFu;
+    if (share > 31) {
+        err = "root share exponent must be at most 31";
+        return -1;
+    }
     if (forced >= p.k) {
         err = "forced root vertex out of range";
         return -1;
@@ -667,15 +901,25 @@ int build_plan(uint32_t k, uint32_t n_arcs, const uint8_t* arcs, uint32_t flags,
 
     CoverReport cr = analyse_cover(p, gs, start);
 
-    // Choose the enumerated set / leaf group.
+    // Candidate plans: a leaf group (trailing independent vertices counted by
+    // product, section 5.3) and an order of the enumerated vertices (section
+    // 5.1).  Each candidate's descriptors decide which arcs the kernel reads
+    // from the data graph (its realized constraint cover, section 4.2) and
+    // which it takes from an including arc's candidate set (section 5.2).
+    // The reduced plan keeps the most leaves, then the smallest weight of
+    // its realized cover (the paper's objective argmin sum ||A_e|| with each
+    // ||A_e|| the estimated list reads of that arc in the plan's context),
+    // then the smaller enumeration estimate.
     Cand best;
     bool have = false;
+    Built bb;
     if (reduced) {
         for (uint32_t L = 0; L <= allv; L++) {
             if (L & (1u << start)) continue;
             if (L == 0) continue;
             int t = popc(L);
             if (t > kMaxLeaves || t >= p.k) continue;
+            if (have && t < (int)best.leaves.size()) continue;
             bool indep = true;
             for (int v = 0; v < p.k && indep; v++)
                 if ((L & (1u << v)) && (p.nbr(v) & L)) indep = false;
@@ -689,24 +933,26 @@ int build_plan(uint32_t k, uint32_t n_arcs, const uint8_t* arcs, uint32_t flags,
                     if (std::find(sigs.begin(), sigs.end(), s) == sigs.end()) sigs.push_back(s);
                 }
             if ((int)sigs.size() > kMaxSig) continue;
-            Cand c;
-            c.order = enum_order(p, start, E);
+            std::vector<int> leaves;
             for (int v = 0; v < p.k; v++)
-                if (L & (1u << v)) c.leaves.push_back(v);
-            c.cost = model_cost(p, c.order, (int)sigs.size(), gs);
-            if (!have || c.leaves.size() > best.leaves.size() ||
-                (c.leaves.size() == best.leaves.size() && c.cost < best.cost * (1 - 1e-9))) {
-                // check the term budget
-                std::sort(sigs.begin(), sigs.end());
-                std::vector<int> ls;
-                for (int v : c.leaves) {
-                    LeafSig s{p.in[v], p.out[v]};
-                    ls.push_back((int)(std::find(sigs.begin(), sigs.end(), s) - sigs.begin()));
+                if (L & (1u << v)) leaves.push_back(v);
+            for (const std::vector<int>& ord : enum_orders(p, start, E)) {
+                Built c;
+                if (!build_desc(p, ord, leaves, true, c)) continue;  // term budget
+                c.cost = model_cost(p, ord, (int)sigs.size(), gs);
+                c.cover_w = cover_weight(p, c, gs);
+                const bool better =
+                    !have || leaves.size() > best.leaves.size() ||
+                    (leaves.size() == best.leaves.size() &&
+                     (c.cover_w < bb.cover_w * (1 - 1e-9) ||
+                      (c.cover_w <= bb.cover_w * (1 + 1e-9) && c.cost < best.cost * (1 - 1e-9))));
+                if (better) {
+                    best.order = ord;
+                    best.leaves = leaves;
+                    best.cost = c.cost;
+                    bb = c;
+                    have = true;
                 }
-                std::vector<Term> tt;
-                if (!leaf_terms(ls, tt)) continue;
-                best = c;
-                have = true;
             }
         }
     }
@@ -716,91 +962,15 @@ int build_plan(uint32_t k, uint32_t n_arcs, const uint8_t* arcs, uint32_t flags,
         best.order.assign(ord.begin(), ord.end() - 1);
         best.leaves = {ord.back()};
         best.cost = model_cost(p, best.order, 1, gs);
+        build_desc(p, best.order, best.leaves, false, bb);
+        bb.cover_w = cover_weight(p, bb, gs);
     }
-
-    std::memset(&D, 0, sizeof(D));
-    D.k = k;
-    D.e = (uint32_t)best.order.size();
-    std::vector<int> lvl_of(p.k, -1);
-    for (size_t i = 0; i < best.order.size(); i++) lvl_of[best.order[i]] = (int)i;
-    for (size_t i = 0; i < best.order.size(); i++) D.order[i] = (uint8_t)best.order[i];
-    D.root_dout = (uint32_t)p.dout(start);
-    D.root_din = (uint32_t)p.din(start);
-    uint32_t leaf_mask = 0;
-    for (int v : best.leaves) leaf_mask |= 1u << v;
-    for (uint32_t i = 1; i < D.e; i++) {
-        int v = best.order[i];
-        uint32_t later = leaf_mask;
-        for (size_t j = i + 1; j < best.order.size(); j++) later |= 1u << best.order[j];
-        fill_level(p, lvl_of, v, (int)i, later, D.lvl[i]);
-        if (reduced && i >= 2) choose_reuse(D, D.lvl[i], (int)i - 1, D.lvl[i].dmin_out, D.lvl[i].dmin_in);
-    }
-    // Leaf signatures.
-    std::vector<LeafSig> sigs;
-    for (int v : best.leaves) {
-        LeafSig s{p.in[v], p.out[v]};
-        if (std::find(sigs.begin(), sigs.end(), s) == sigs.end()) sigs.push_back(s);
-    }
-    std::sort(sigs.begin(), sigs.end());
-    D.n_sig = (uint32_t)sigs.size();
-    D.t = (uint32_t)best.leaves.size();
-    std::vector<int> leaf_sig;
-    for (int v : best.leaves) {
-        LeafSig s{p.in[v], p.out[v]};
-        int g = (int)(std::find(sigs.begin(), sigs.end(), s) - sigs.begin());
-        leaf_sig.push_back(g);
-        D.sig_mult[g]++;
-    }
-    for (uint32_t g = 0; g < D.n_sig; g++) {
-        // any leaf of this signature gives the same constraint set
-        int v = -1;
-        for (size_t i = 0; i < best.leaves.size(); i++)
-            if (leaf_sig[i] == (int)g) v = best.leaves[i];
-        fill_level(p, lvl_of, v, (int)D.e, 0u, D.sig[g]);
-        D.sig[g].dmin_out = D.sig[g].dmin_in = 0;  // implied by the constraints of a leaf
-        D.sig[g].deg_check = 0;
-        if (reduced && D.e >= 2)
-            choose_reuse(D, D.sig[g], (int)D.e - 1, (uint32_t)p.dout(v), (uint32_t)p.din(v));
-    }
-    std::vector<Term> terms;
-    leaf_terms(leaf_sig, terms);
-    D.n_terms = (uint32_t)terms.size();
-    for (size_t i = 0; i < terms.size(); i++) D.terms[i] = terms[i];
-    D.linear = (D.t == 1) ? 1 : 0;
-    for (size_t i = 0; i < best.leaves.size(); i++) D.order[D.e + i] = (uint8_t)best.leaves[i];
-    // one candidate test per signature mask the terms use
-    {
-        uint32_t used = 0;
-        for (uint32_t i = 0; i < D.n_terms; i++)
-            for (int b = 0; b < D.terms[i].nb; b++) used |= 1u << D.terms[i].mask[b];
-        D.n_masks = 0;
-        for (uint32_t M = 1; M < 16; M++) {
-            if (!((used >> M) & 1u)) continue;
-            uint32_t in = 0, out = 0;
-            for (uint32_t g = 0; g < D.n_sig; g++)
-                if ((M >> g) & 1u) {
-                    in |= sigs[g].in_mask;
-                    out |= sigs[g].out_mask;
-                }
-            LevelDesc L;
-            std::memset(&L, 0, sizeof L);
-            fill_level_sig(p, lvl_of, in, out, (int)D.e, L);
-            // a node in every set of M has all of M's arcs to bound nodes
-            if (reduced && D.e >= 2) choose_reuse(D, L, (int)D.e - 1, (uint32_t)popc(out), (uint32_t)popc(in));
-            // a mask whose test equals an earlier one's has the same set
-            uint32_t j = 0;
-            while (j < D.n_masks && std::memcmp(&D.mdesc[j], &L, sizeof L) != 0) j++;
-            if (j == D.n_masks) {
-                D.mdesc[j] = L;
-                D.mask_id[j] = (uint8_t)M;
-                D.mask_set[j] = 0;
-                D.n_masks++;
-            }
-            D.mask_set[j] |= (uint16_t)(1u << M);
-        }
-    }
+    D = bb.D;
     D.sym_mult = 1;
-    if (flags & 0x4u) apply_symmetry(p, D, (flags & 0x8u) != 0, forced >= 0);
+    D.root_share = (uint8_t)share;
+    // a root share is a root subset: symmetry breaking then keeps only the
+    // automorphisms that fix the start vertex, so every orbit stays in it
+    if (flags & 0x4u) apply_symmetry(p, D, (flags & 0x8u) != 0, forced >= 0 || share > 0);
     // packed constraint fields read by the kernel
     auto pack = [](LevelDesc& L) {
         L.dir_mask = 0;
@@ -813,7 +983,10 @@ int build_plan(uint32_t k, uint32_t n_arcs, const uint8_t* arcs, uint32_t flags,
     for (uint32_t i = 1; i < D.e; i++) pack(D.lvl[i]);
     for (uint32_t g = 0; g < D.n_sig; g++) pack(D.sig[g]);
     for (uint32_t i = 0; i < D.n_masks; i++) pack(D.mdesc[i]);
-    json = plan_json(p, D, cr, reduced, best.cost);
+    // the realized cover after symmetry breaking (which may drop a reuse)
+    bb.D = D;
+    const uint64_t fetched = fetched_arcs(p, bb);
+    json = plan_json(p, D, cr, reduced, best.cost, fetched, cover_weight(p, bb, gs));
     return 0;
 }
 

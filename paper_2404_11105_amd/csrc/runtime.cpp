@@ -25,10 +25,12 @@ struct xm_graph_s {
     const uint32_t *out_off = nullptr, *out_adj = nullptr, *in_off = nullptr, *in_adj = nullptr;
     bool owns_csr = false;
     uint2* deg = nullptr;         // device, owned
+    uint8_t* degc = nullptr;      // device, owned: per node min(out, 15) | min(in, 15) << 4
     uint32_t* hubs = nullptr;     // device, owned
     uint32_t n_hubs = 0;
     std::vector<uint32_t> hub_len;  // host: longest list of each hub (queue sizing)
     std::vector<uint2> hub_deg;     // host: (out, in) degree of each hub
+    std::vector<uint32_t> hub_id;   // host: node id of each hub
     uint32_t max_out = 0, max_in = 0;
     std::vector<uint2> hdeg;        // host: (out, in) degree per node
     std::vector<uint32_t> new_of_old;  // XM_ORDER_BY_DEGREE: the renumbering (empty: none)
@@ -105,6 +107,7 @@ struct Layout {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr uint64_t kMaxQueueBytes = 2ull << 30;  // split task queue, at most
+constexpr uint64_t kMaxRootItems = 0xFFFFFFFFull - 64;  // root items per launch (32-bit item ids)
 
 int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* plans,
                 const xm_count_opts* o, Layout& L) {
@@ -185,6 +188,13 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
         const uint64_t per = (uint64_t)L.n_waves * 64;
         L.chunk = (uint32_t)std::min<uint64_t>(64, std::max<uint64_t>(1, (n_src * n_plans + per - 1) / per));
     }
+    {
+        // root items (plan, chunk) are numbered in 32 bits
+        const uint64_t n_src = (o && o->roots_dev) ? o->n_roots : g->n;
+        const uint64_t items = (n_src + L.chunk - 1) / L.chunk * n_plans;
+        if (items > kMaxRootItems)
+            return fail(XM_ERR_INVALID, "too many root items (roots x plans / chunk >= 2^32); raise chunk");
+    }
     if ((size_t)L.lds_words * 4 * xm::kWavesPerBlock > g->max_lds_block)
         return fail(XM_ERR_INVALID, "plans need more LDS than a workgroup may use");
     // split task queue capacity
@@ -214,6 +224,7 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
                     const uint2 d = g->hdeg[r];
                     if (std::max(d.x, d.y) <= xm::kHubMin) continue;  // the split kernel's cut
                     if (d.x < D.root_dout || d.y < D.root_din) continue;
+                    if (!xm::in_root_share(r, D.root_share)) continue;
                     uint32_t L1 = 0xFFFFFFFFu;
                     for (int c = 0; c < D.lvl[1].n_cons; c++) L1 = std::min(L1, D.lvl[1].cons_dir[c] ? d.y : d.x);
                     const uint64_t pc = pieces(L1, sw, D.e);
@@ -236,6 +247,7 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
             for (size_t h = 0; h < g->hub_deg.size(); h++) {
                 uint2 d = g->hub_deg[h];
                 if (d.x < D.root_dout || d.y < D.root_din) continue;
+                if (!xm::in_root_share(g->hub_id[h], D.root_share)) continue;
                 uint32_t L1 = 0xFFFFFFFFu;
                 for (int c = 0; c < D.lvl[1].n_cons; c++) L1 = std::min(L1, D.lvl[1].cons_dir[c] ? d.y : d.x);
                 const uint64_t pc = pieces(L1, sw, D.e);
@@ -293,6 +305,7 @@ int enqueue_count(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const*
     a.g.in_off = g->in_off;
     a.g.in_adj = g->in_adj;
     a.g.deg = g->deg;
+    a.g.degc = g->degc;
     a.g.n = g->n;
     a.g.row_min = g->rows ? g->row_min : xm::kNoRows;
     a.g.rows = g->rows;
@@ -427,6 +440,7 @@ int xm_load_graph(uint32_t n, uint32_t m, const uint32_t* out_off, const uint32_
             (void)hipFree((void*)g->in_adj);
         }
         if (g->deg) (void)hipFree(g->deg);
+        if (g->degc) (void)hipFree(g->degc);
         if (g->hubs) (void)hipFree(g->hubs);
         delete g;
     };
@@ -559,10 +573,12 @@ int xm_load_graph(uint32_t n, uint32_t m, const uint32_t* out_off, const uint32_
     g->n_hubs = (uint32_t)hubs.size();
     g->hub_len.resize(hubs.size());
     g->hub_deg.resize(hubs.size());
+    g->hub_id.resize(hubs.size());
     std::vector<uint32_t> hub_ids(std::max<size_t>(hubs.size(), 1), 0);
     for (size_t i = 0; i < hubs.size(); i++) {
         g->hub_len[i] = hubs[i].first;
         g->hub_deg[i] = deg[hubs[i].second];
+        g->hub_id[i] = hubs[i].second;
         hub_ids[i] = hubs[i].second;
     }
     g->stats.n = n;
@@ -572,13 +588,21 @@ int xm_load_graph(uint32_t n, uint32_t m, const uint32_t* out_off, const uint32_
         g->stats.frac_in_ge[t] = (double)ge_in[t] / n;
     }
     g->hdeg = deg;
+    // degree classes for the candidate tests: thresholds never pass 6 (a
+    // pattern vertex has at most 6 out- and 6 in-neighbours), so degrees
+    // capped at 15 decide them exactly, one byte per node
+    std::vector<uint8_t> degc(n);
+    for (uint32_t v = 0; v < n; v++)
+        degc[v] = (uint8_t)(std::min<uint32_t>(deg[v].x, 15u) | (std::min<uint32_t>(deg[v].y, 15u) << 4));
     if ((e = hipMalloc(&g->deg, (size_t)n * sizeof(uint2))) != hipSuccess ||
+        (e = hipMalloc(&g->degc, (size_t)n)) != hipSuccess ||
         (e = hipMalloc(&g->hubs, hub_ids.size() * 4)) != hipSuccess) {
         cleanup();
         return fail(XM_ERR_OOM, "hipMalloc(degrees)");
     }
     if ((e = hipMemcpyAsync(g->deg, deg.data(), (size_t)n * sizeof(uint2), hipMemcpyHostToDevice, stream)) !=
             hipSuccess ||
+        (e = hipMemcpyAsync(g->degc, degc.data(), (size_t)n, hipMemcpyHostToDevice, stream)) != hipSuccess ||
         (e = hipMemcpyAsync(g->hubs, hub_ids.data(), hub_ids.size() * 4, hipMemcpyHostToDevice, stream)) !=
             hipSuccess ||
         (e = hipStreamSynchronize(stream)) != hipSuccess) {
@@ -597,11 +621,34 @@ int xm_plan_work(uint32_t n, const uint32_t* out_off, const uint32_t* out_adj, c
         return fail(XM_ERR_INVALID, "NULL adjacency array");
     xm::HostCsr h{out_off, out_adj, in_off, in_adj, n};
     xm::WorkOut w;
-    bool exceeded = xm::plan_work(h, p->desc, roots, n_roots, threads ? threads : 1, max_partial, w);
+    bool exceeded = xm::plan_work(h, p->desc, roots, n_roots, threads ? threads : 1, max_partial, xm::kNoRows, w);
     out[0] = w.elements;
     out[1] = w.fetches;
     out[2] = w.partial;
     out[3] = w.roots;
+    return exceeded ? 1 : XM_OK;
+}
+
+int xm_plan_traffic(uint32_t n, const uint32_t* out_off, const uint32_t* out_adj, const uint32_t* in_off,
+                    const uint32_t* in_adj, const xm_plan_t* p, const uint32_t* roots, uint32_t n_roots,
+                    uint32_t row_min, uint32_t threads, uint64_t max_partial, uint64_t out[XM_TRAFFIC_WORDS]) {
+    if (!p || !out || !out_off || !in_off || n == 0) return fail(XM_ERR_INVALID, "NULL argument");
+    if ((out_off[n] > 0 && !out_adj) || (in_off[n] > 0 && !in_adj))
+        return fail(XM_ERR_INVALID, "NULL adjacency array");
+    xm::HostCsr h{out_off, out_adj, in_off, in_adj, n};
+    xm::WorkOut w;
+    bool exceeded = xm::plan_work(h, p->desc, roots, n_roots, threads ? threads : 1, max_partial,
+                                  row_min ? row_min : xm::kNoRows, w);
+    out[0] = w.base;
+    out[1] = w.offset_pairs;
+    out[2] = w.deg_reads;
+    out[3] = w.row_probes;
+    out[4] = w.searches;
+    out[5] = w.search_words;
+    out[6] = w.partial;
+    out[7] = w.chain_words;
+    out[8] = w.roots;
+    out[9] = w.elements;
     return exceeded ? 1 : XM_OK;
 }
 
@@ -615,6 +662,7 @@ int xm_free_graph(xm_graph_t* g) {
         (void)hipFree((void*)g->in_adj);
     }
     if (g->deg) (void)hipFree(g->deg);
+    if (g->degc) (void)hipFree(g->degc);
     if (g->hubs) (void)hipFree(g->hubs);
     if (g->rows) (void)hipFree(g->rows);
     if (g->row_of) (void)hipFree(g->row_of);
@@ -756,7 +804,7 @@ int xm_plan(uint32_t k, uint32_t n_arcs, const uint8_t* arcs, uint32_t flags, co
             xm_plan_t** out) {
     if (!out) return fail(XM_ERR_INVALID, "out is NULL");
     *out = nullptr;
-    if (flags & ~(0xFu | 0xF00u)) return fail(XM_ERR_INVALID, "unknown plan flag");
+    if (flags & ~(0xFu | 0xF00u | 0xFF0000u)) return fail(XM_ERR_INVALID, "unknown plan flag");
     xm_plan_t* p = new (std::nothrow) xm_plan_s;
     if (!p) return fail(XM_ERR_OOM, "host allocation");
     std::string err;

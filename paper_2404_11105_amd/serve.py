@@ -38,6 +38,7 @@ from concurrent.futures import Future
 
 XM_ERR_CANCELLED = -7
 XM_ERR_ADMISSION = -9  # serving-level status: the request can never fit the budget
+XM_ERR_SERVER = -10    # serving-level status: planning, sizing or launching raised
 
 
 @dataclasses.dataclass
@@ -184,12 +185,20 @@ class Server:
         self.completed.append(r)
         r.future.set_result((count, status))
 
+    @staticmethod
+    def _code(exc) -> int:
+        code = getattr(exc, "code", None)
+        return code if isinstance(code, int) and code < 0 else XM_ERR_SERVER
+
     def _reap(self):
         for si in list(self.busy):
             handle, reqs, fp = self.busy[si]
-            if not self.backend.poll(handle):
-                continue
-            counts, status = self.backend.results(handle)
+            try:
+                if not self.backend.poll(handle):
+                    continue
+                counts, status = self.backend.results(handle)
+            except Exception as exc:  # a failed launch ends its requests, not the loop
+                counts, status = [None] * len(reqs), [self._code(exc)] * len(reqs)
             for r, c, s in zip(reqs, counts, status):
                 self._finish(r, s, c if s == 0 else None)
             self.in_use -= fp
@@ -205,7 +214,13 @@ class Server:
                 self._finish(head, XM_ERR_CANCELLED, None)
                 continue
             sjf = self.policy == "sjf"
-            est = lambda r: self.backend.cost(r.graph_id, r.pattern, r.pin[0] if r.pin else None)  # noqa: E731
+
+            def est(r):
+                # a request that cannot be planned sorts last and fails below
+                try:
+                    return self.backend.cost(r.graph_id, r.pattern, r.pin[0] if r.pin else None)
+                except Exception:
+                    return float("inf")
             if sjf and now - head.submitted <= self.age_s:
                 # the cheapest pending request leads; the rest keep arrival order
                 head = min(self.pending, key=lambda r: (est(r), r.rid))
@@ -226,13 +241,30 @@ class Server:
                     batch.append(r)
                 else:
                     rest.append(r)
+            # plan every request; one that cannot be planned fails on its own
+            plans, ok = [], []
+            for r in batch:
+                try:
+                    plans.append(self.backend.plan(r.graph_id, r.pattern, r.pin[0] if r.pin else None))
+                    ok.append(r)
+                except Exception as exc:
+                    self._finish(r, self._code(exc), None)
+            batch = ok
+            if not batch:
+                self.pending = collections.deque(sorted(rest, key=lambda q: q.rid))
+                continue
             # shrink the batch until it fits the free budget
-            plans = [self.backend.plan(r.graph_id, r.pattern, r.pin[0] if r.pin else None) for r in batch]
-            fp = self.backend.footprint(head.graph_id, plans, node)
-            while fp > self.hbm_budget - self.in_use and len(batch) > 1:
-                rest.appendleft(batch.pop())
-                plans.pop()
+            try:
                 fp = self.backend.footprint(head.graph_id, plans, node)
+                while fp > self.hbm_budget - self.in_use and len(batch) > 1:
+                    rest.appendleft(batch.pop())
+                    plans.pop()
+                    fp = self.backend.footprint(head.graph_id, plans, node)
+            except Exception as exc:
+                for r in batch:
+                    self._finish(r, self._code(exc), None)
+                self.pending = collections.deque(sorted(rest, key=lambda q: q.rid))
+                continue
             if fp > self.hbm_budget:
                 # even alone this request can never fit
                 self._finish(batch[0], XM_ERR_ADMISSION, None)
@@ -243,8 +275,14 @@ class Server:
                 self.pending = collections.deque(sorted(list(rest) + batch, key=lambda q: q.rid))
                 break
             self.pending = collections.deque(sorted(rest, key=lambda q: q.rid))
-            si = free.pop(0)
-            handle = self.backend.launch(self.slots[si], head.graph_id, plans, node)
+            si = free[0]
+            try:
+                handle = self.backend.launch(self.slots[si], head.graph_id, plans, node)
+            except Exception as exc:
+                for r in batch:
+                    self._finish(r, self._code(exc), None)
+                continue
+            free.pop(0)
             self.busy[si] = (handle, batch, fp)
             self.in_use += fp
             self.launches += 1

@@ -31,6 +31,9 @@ class Model:
                      [set(self.in_adj[self.in_off[v]:self.in_off[v + 1]].tolist()) for v in range(graph.n)])
         self.windows = 0
         self.max_windows = max_windows
+        # lists read from the data graph: (descriptor, constraint index,
+        # whether the read replaced an unavailable reuse source)
+        self.reads = set()
         e = plan["e"]
         self.F = [dict(node=[0] * cap, parent=[0] * cap, segb=[0] * cap, segc=[0] * cap, aux=[0] * cap)
                   for _ in range(max(e, 1))]
@@ -61,7 +64,7 @@ class Model:
         return self.out_off[x + 1] - self.out_off[x], self.in_off[x + 1] - self.in_off[x]
 
     # ---- phase A for one parent p of level lv (or prefix p of level lv-1 for sigs)
-    def phase_a(self, D, lv, p, is_sig, bound, anc):
+    def phase_a(self, D, lv, p, is_sig, bound, anc, tag=None):
         meta = {}
         fetched = False
         if D["reuse"] >= 0:
@@ -78,9 +81,12 @@ class Model:
                 for c, (j, d) in enumerate(D["cons"]):
                     if (D["extra"] >> c) & 1:
                         chk.append((d,) + self.lst(bound[j], d) + (bound[j],))
+                        self.reads.add((tag, c, False))
                 meta["chk"] = chk
                 fetched = True
         if not fetched:
+            for c in range(len(D["cons"])):
+                self.reads.add((tag, c, D["reuse"] >= 0))
             lists = [(d,) + self.lst(bound[j], d) + (bound[j],) for j, d in D["cons"]]
             bi = min(range(len(lists)), key=lambda i: (lists[i][2], i))
             meta["kind"] = lists[bi][0]
@@ -152,7 +158,7 @@ class Model:
                 metas.append(None)
                 continue
             bound, anc = self.chain(lv - 1, p)
-            m = self.phase_a(D, lv, p, False, bound, anc)
+            m = self.phase_a(D, lv, p, False, bound, anc, tag=("lvl", lv))
             m["bound"] = bound
             ln = m["len"] - (pofs if lane == 0 else 0)
             assert ln >= 0, "negative remaining length"
@@ -213,6 +219,7 @@ class Model:
                 bound, anc = self.chain(lv, p)
                 S0 = sigs[0]
                 if P["linear"] and len(S0["cons"]) == 1 and S0["reuse"] < 0:
+                    self.reads.add((("sig", 0), 0, False))
                     j, d = S0["cons"][0]
                     lo, hi = self._rng(bound[j], d)
                     L = self.sets[d][bound[j]]
@@ -230,8 +237,9 @@ class Model:
                 # several signatures: h[M] = |intersection of the sets in M| for
                 # every mask the terms use, then the inclusion-exclusion terms
                 hist = [0] * 16
-                for M in P["masks"]:
+                for mi, M in enumerate(P["masks"]):
                     if len(M["cons"]) == 1 and M["reuse"] < 0:
+                        self.reads.add((("mask", mi), 0, False))
                         j, d = M["cons"][0]
                         L = self.sets[d][bound[j]]
                         lo, hi = self._rng(bound[j], d)
@@ -239,7 +247,7 @@ class Model:
                             hist[mm] = (hi - lo) - sum(1 for b in range(lv + 1)
                                                        if (M["inj"] >> b) & 1 and bound[b] in L)
                         continue
-                    m = self.phase_a(M, lv + 1, p, True, bound, anc)
+                    m = self.phase_a(M, lv + 1, p, True, bound, anc, tag=("mask", mi))
                     cnt = 0
                     for local in range(m["len"]):
                         x = self.base_elem(m, local, M["reuse"])
@@ -286,8 +294,12 @@ class Model:
         P, g = self.P, self.g
         rdo, rdi = P["root_dmin"]
         items = []
+        share = P.get("root_share", 0)
+        in_share = lambda r: (r + 1) % (1 << share) == 0  # noqa: E731
         if P["e"] >= 2:
             for r in range(g.n):
+                if not in_share(r):
+                    continue
                 do, di = self.deg(r)
                 if do < rdo or di < rdi:
                     continue
@@ -305,6 +317,8 @@ class Model:
             n0 = 0
             # chunk c0 takes the roots c0, c0 + n_chunks, ... (strided)
             for r in range(c0, g.n, n_chunks)[: self.chunk]:
+                if not in_share(r):
+                    continue
                 do, di = self.deg(r)
                 if do < rdo or di < rdi:
                     continue

@@ -173,3 +173,55 @@ def test_sjf_runs_cheap_requests_first_without_starving_heavy_ones():
     done = {r.rid: r.done for r in s.completed}
     s.close()
     assert all(done[1] < done[i] for i in (2, 3, 4))
+
+
+class FailingBackend(FakeBackend):
+    """Raises from plan (patterns with 4 vertices), footprint (graph "r" with
+    2 or more plans) or launch (a c3 in the batch), like a library error or
+    an out-of-memory during set-up would."""
+
+    def plan(self, graph_id, pattern, pin_vertex=None):
+        if pattern.k == 4:
+            from paper_2404_11105_amd._lib import XminerError
+            raise XminerError(-2, "pattern rejected")
+        return super().plan(graph_id, pattern, pin_vertex)
+
+    def cost(self, graph_id, pattern, pin_vertex=None):
+        self.plan(graph_id, pattern, pin_vertex)
+        return super().cost(graph_id, pattern, pin_vertex)
+
+    def footprint(self, graph_id, plans, node=None):
+        if graph_id == "r" and len(plans) >= 2:
+            raise MemoryError("workspace sizing failed")
+        return super().footprint(graph_id, plans, node)
+
+    def launch(self, slot, graph_id, plans, node=None):
+        if any(p.name == "c3" for p, _ in plans):
+            raise RuntimeError("launch failed")
+        return super().launch(slot, graph_id, plans, node)
+
+
+@pytest.mark.parametrize("policy", ["fifo", "sjf"])
+def test_backend_errors_fail_their_requests_and_keep_serving(policy):
+    gs = graphs()
+    be = FailingBackend(gs)
+    srv = Server(be, hbm_budget=10_000, slots=2, max_batch=4, policy=policy)
+    reqs = [("u", xmgen.named(n)) for n in ["ffl", "bifan", "c3", "path3", "ffl"]]
+    reqs += [("r", xmgen.named("ffl")), ("r", xmgen.named("path3"))]
+    futs = [srv.submit(g, p) for g, p in reqs]
+    res = [f.result(timeout=30) for f in futs]
+    # the loop is still alive: a later request on a healthy batch completes
+    late = srv.submit("u", xmgen.named("path3")).result(timeout=30)
+    srv.close()
+    for (gid, p), (c, s) in zip(reqs, res):
+        if p.k == 4:
+            assert s == -2 and c is None  # the plan's own error code
+        elif gid == "r" or s != 0:
+            assert s < 0 and c is None
+        else:
+            assert c == oracle.count(gs[gid], p)
+    assert res[1][1] == -2
+    assert late == (oracle.count(gs["u"], xmgen.named("path3")), 0)
+    # every request on graph "r" shares a batch whose sizing raised, unless
+    # it ran alone; none of them hangs
+    assert all(s in (0, -10) for (gid, _), (_, s) in zip(reqs, res) if gid == "r")
