@@ -237,6 +237,17 @@ struct Walker {
         }
     }
 
+    // Budget accounting: partial matches plus merge-model elements / 256 (a
+    // leaf pass over hub lists does much work per partial match).
+    void charge() {
+        const uint64_t units = w.partial + w.elements / 256;
+        if (budget && units - reported >= 4096) {
+            uint64_t tot = shared_partial->fetch_add(units - reported) + (units - reported);
+            reported = units;
+            if (tot > budget) stop = true;
+        }
+    }
+
     void level(uint32_t lv) {
         if (stop) return;
         if (lv == P.e) {
@@ -259,18 +270,12 @@ struct Walker {
             if (test(D, D.inj, lv, probe_l, plen, np, x)) out.push_back(x);
         }
         w.partial += out.size();
-        // the budget also bounds the merge-model elements (256 per partial
-        // match): a leaf pass over hub lists does much work per match
-        const uint64_t units = w.partial + w.elements / 256;
-        if (budget && units - reported >= 4096) {
-            uint64_t tot = shared_partial->fetch_add(units - reported) + (units - reported);
-            reported = units;
-            if (tot > budget) stop = true;
-        }
+        charge();
         // deeper levels only write cand[> lv], so cand[lv] stays valid for reuse
-        for (size_t i = 0; i < cand[lv].size(); i++) {
+        for (size_t i = 0; i < cand[lv].size() && !stop; i++) {
             phi[lv] = cand[lv][i];
             level(lv + 1);
+            charge();
         }
     }
 
