@@ -326,6 +326,22 @@ int xm_count(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* plan
              const xm_count_opts* opts, void* workspace, size_t ws_bytes,
              uint64_t* counts_dev, int32_t* status_dev, void* hip_stream);
 
+/* xm_count without a workspace, for callers that cannot allocate device
+ * memory (code under HIP-graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The workspace is a fixed array of
+ * XM_STATIC_SCRATCH_BYTES in device memory that the library holds on every
+ * device it runs on until the process ends; the call allocates nothing (plan
+ * descriptors travel to the device in kernel arguments).  Same arguments and
+ * results as xm_count otherwise; fields of opts left 0 take smaller defaults
+ * here (cap 256, 4 waves per compute unit).  A launch whose workspace
+ * (xm_workspace_size with those defaults) would pass the array fails with
+ * XM_ERR_WORKSPACE before anything is enqueued.  Every call on one device
+ * shares that device's array: calls that overlap in time on one device race
+ * and give wrong counts; the call itself clears what must start at zero. */
+#define XM_STATIC_SCRATCH_BYTES (64ull << 20)
+int xm_count_static(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* plans,
+                    const xm_count_opts* opts, uint64_t* counts_dev, int32_t* status_dev, void* hip_stream);
+
 /* ----------------------------------------------------------------------------
  * HIP-graph form of xm_count: records the same launches once (captured on
  * hip_stream) and instantiates them; xm_exec_launch replays them with the

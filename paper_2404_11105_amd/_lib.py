@@ -73,7 +73,8 @@ class XminerError(RuntimeError):
 EXPORTS = [
     "xm_load_graph", "xm_free_graph", "xm_graph_info", "xm_graph_node_order", "xm_graph_dense_rows", "xm_graph_dense_rows_info",
     "xm_plan", "xm_plan_describe",
-    "xm_plan_root_vertex", "xm_free_plan", "xm_plan_work", "xm_plan_traffic", "xm_workspace_size", "xm_count", "xm_count_capture",
+    "xm_plan_root_vertex", "xm_free_plan", "xm_plan_work", "xm_plan_traffic", "xm_workspace_size", "xm_count",
+    "xm_count_static", "xm_count_capture",
     "xm_exec_launch", "xm_free_exec", "xm_strerror", "xm_last_error", "xm_version",
 ]
 
@@ -104,6 +105,7 @@ def lib():
         L.xm_workspace_size.argtypes = [P, U32, P, P]
         L.xm_workspace_size.restype = SZ
         L.xm_count.argtypes = [P, U32, P, P, P, SZ, P, P, P]
+        L.xm_count_static.argtypes = [P, U32, P, P, P, P, P]
         L.xm_count_capture.argtypes = [P, U32, P, P, P, SZ, P, P, P, ctypes.POINTER(P)]
         L.xm_exec_launch.argtypes = [P, P]
         L.xm_free_exec.argtypes = [P]
@@ -114,7 +116,7 @@ def lib():
         for name in ["xm_load_graph", "xm_free_graph", "xm_graph_info", "xm_graph_dense_rows",
                      "xm_graph_dense_rows_info", "xm_plan",
                      "xm_plan_describe", "xm_plan_root_vertex", "xm_free_plan", "xm_plan_work",
-                     "xm_plan_traffic", "xm_count",
+                     "xm_plan_traffic", "xm_count", "xm_count_static",
                      "xm_count_capture", "xm_exec_launch", "xm_free_exec"]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L

@@ -1297,6 +1297,32 @@ __global__ void finalize_kernel(KArgs a) {
     }
 }
 
+// Workspace of xm_count_static: a fixed array in device memory, one copy per
+// device, so that launches need no allocation.  Host code never uses this
+// name as an address: the address comes from hipGetSymbolAddress.
+static __device__ __align__(256) uint8_t g_static_scratch[kStaticScratchBytes];
+
+hipError_t static_scratch_address(void** ptr) {
+    return hipGetSymbolAddress(ptr, HIP_SYMBOL(g_static_scratch));
+}
+
+__global__ void desc_chunk_kernel(DescChunk c) {
+    for (uint32_t i = threadIdx.x; i < c.n; i += blockDim.x) c.dst[i] = c.w[i];
+}
+
+hipError_t copy_desc(PlanDesc* dst, const PlanDesc& src, hipStream_t stream) {
+    const uint32_t words = sizeof(PlanDesc) / 4;
+    const uint32_t* s = reinterpret_cast<const uint32_t*>(&src);
+    for (uint32_t o = 0; o < words; o += kDescChunkWords) {
+        DescChunk c;
+        c.dst = reinterpret_cast<uint32_t*>(dst) + o;
+        c.n = words - o < kDescChunkWords ? words - o : kDescChunkWords;
+        for (uint32_t i = 0; i < c.n; i++) c.w[i] = s[o + i];
+        hipLaunchKernelGGL(desc_chunk_kernel, dim3(1), dim3(256), 0, stream, c);
+    }
+    return hipGetLastError();
+}
+
 int count_blocks_per_cu(bool nonlin, size_t lds_bytes) {
     int nb = 0;
     hipError_t e;

@@ -20,6 +20,24 @@ constexpr uint32_t kMergeRatio = 16;  // ... and within this length ratio -> mer
 constexpr uint32_t kQueues = 8;  // split-task queues, one per XCD (8 XCDs on MI355X)
 constexpr uint32_t kDonWords = 8;  // donated task: plan | depth << 16, ready flag, prefix nodes [6]
 constexpr uint32_t kDonCap = 1u << 18;  // donated-task slots per launch
+constexpr uint32_t kDonCapStatic = 1u << 14;  // ... in launches on the static scratch array
+
+// The static scratch array of xm_count_static (file scope in count.hip): one
+// copy per device, held until the process ends.
+constexpr uint64_t kStaticScratchBytes = 64ull << 20;
+// Device address of this device's copy (hipGetSymbolAddress; call with the
+// device current).
+hipError_t static_scratch_address(void** ptr);
+
+// Copy one plan descriptor from host memory into dst through kernel
+// arguments (no staging allocation): words of the descriptor in chunks.
+constexpr uint32_t kDescChunkWords = 480;
+struct DescChunk {
+    uint32_t* dst;
+    uint32_t n;
+    uint32_t w[kDescChunkWords];
+};
+hipError_t copy_desc(PlanDesc* dst, const PlanDesc& src, hipStream_t stream);
 
 enum Ctl : uint32_t {
     kCtlCancelled = 3,    // a wave saw the cancel flag

@@ -19,6 +19,8 @@
 
 using xm::PlanDesc;
 
+static_assert(xm::kStaticScratchBytes == XM_STATIC_SCRATCH_BYTES, "static scratch size differs from the header's");
+
 struct xm_graph_s {
     int device = 0;
     uint32_t n = 0, m = 0;
@@ -97,7 +99,7 @@ int plan_device_desc(xm_plan_t* p, int dev, const PlanDesc** out) {
 }
 
 struct Layout {
-    uint32_t chunk, split, split_work, cap, waves_per_cu, n_waves, n_blocks, e_max, maxc, merge_min;
+    uint32_t chunk, split, split_work, cap, waves_per_cu, n_waves, n_blocks, e_max, maxc, merge_min, don_cap;
     bool nonlinear;
     size_t off_ctl, off_flags, off_table, off_split, off_don, off_scratch, total;
     uint32_t split_cap, wave_words, lds_words;
@@ -109,8 +111,13 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 constexpr uint64_t kMaxQueueBytes = 2ull << 30;  // split task queue, at most
 constexpr uint64_t kMaxRootItems = 0xFFFFFFFFull - 64;  // root items per launch (32-bit item ids)
 
+// Defaults of launches on the static scratch array (xm_count_static): fewer
+// resident waves and smaller level windows, so that the workspace of most
+// launches fits the array.
+constexpr uint32_t kStaticCap = 256, kStaticWavesPerCu = 4;
+
 int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* plans,
-                const xm_count_opts* o, Layout& L) {
+                const xm_count_opts* o, Layout& L, bool on_static = false) {
     if (!g) return fail(XM_ERR_INVALID, "graph is NULL");
     if (n_plans == 0 || !plans) return fail(XM_ERR_INVALID, "no plans");
     if (n_plans > 65535) return fail(XM_ERR_INVALID, "at most 65535 plans per launch");
@@ -132,11 +139,13 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
     L.chunk = (o && o->chunk) ? o->chunk : 0;  // 0: sized below from the task count
     L.split = (o && o->split) ? o->split : 64;
     L.split_work = (o && o->split_work) ? o->split_work : 4096;
-    L.cap = (o && o->cap) ? o->cap : 4096;
-    L.waves_per_cu = (o && o->waves_per_cu) ? o->waves_per_cu : 0;  // 0: from occupancy
+    L.cap = (o && o->cap) ? o->cap : (on_static ? kStaticCap : 4096);
+    L.waves_per_cu = (o && o->waves_per_cu) ? o->waves_per_cu : (on_static ? kStaticWavesPerCu : 0);  // 0: from occupancy
+    L.don_cap = on_static ? xm::kDonCapStatic : xm::kDonCap;
     if (L.chunk > 64) return fail(XM_ERR_INVALID, "chunk must be <= 64");
     if (L.split < xm::kHubMin) return fail(XM_ERR_INVALID, "split must be >= 64");
     if (L.split_work < xm::kHubMin * xm::kHubMin) return fail(XM_ERR_INVALID, "split_work must be >= 4096");
+    if (on_static && !(o && o->split) && L.cap < L.split) L.split = L.cap;
     if (L.cap < L.split || L.cap < 64) return fail(XM_ERR_INVALID, "cap must be >= split and >= 64");
     if (L.cap > (1u << 24)) return fail(XM_ERR_INVALID, "cap too large");
     if (L.waves_per_cu != 0 && (L.waves_per_cu < 4 || L.waves_per_cu > 32))
@@ -277,19 +286,48 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
     L.off_split = off;
     off = align256(off + (size_t)L.split_cap * 16);
     L.off_don = off;
-    off = align256(off + (size_t)xm::kDonCap * xm::kDonWords * 4);
+    off = align256(off + (size_t)L.don_cap * xm::kDonWords * 4);
     L.off_scratch = off;
     off = align256(off + (size_t)L.n_waves * L.wave_words * 4);
     L.total = off;
     return XM_OK;
 }
 
+// Device address of the static scratch array on the current device, looked
+// up once per device (each device holds its own copy).
+int static_scratch(int dev, void** out) {
+    static std::mutex mu;
+    static std::vector<void*> addr;
+    std::lock_guard<std::mutex> lk(mu);
+    if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(xm::static_scratch_address(&p), "hipGetSymbolAddress(static scratch)");
+        if (!p) return fail(XM_ERR_HIP, "hipGetSymbolAddress(static scratch) returned NULL");
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return XM_OK;
+}
+
 int enqueue_count(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* plans,
                   const xm_count_opts* o, void* ws, size_t ws_bytes, uint64_t* counts,
-                  int32_t* status, hipStream_t stream) {
+                  int32_t* status, hipStream_t stream, bool on_static = false) {
     Layout L;
-    int rc = make_layout(g, n_plans, plans, o, L);
+    int rc = make_layout(g, n_plans, plans, o, L, on_static);
     if (rc) return rc;
+    if (on_static) {
+        if (L.total > xm::kStaticScratchBytes)
+            return fail(XM_ERR_WORKSPACE, "launch needs " + std::to_string(L.total) +
+                                              " bytes of workspace, more than the static scratch array holds (" +
+                                              std::to_string(xm::kStaticScratchBytes) +
+                                              "); lower cap or waves_per_cu, or use xm_count");
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+        rc = static_scratch(dev, &ws);
+        if (rc) return rc;
+        ws_bytes = xm::kStaticScratchBytes;
+    }
     if (!ws || ws_bytes < L.total) return fail(XM_ERR_WORKSPACE, "workspace missing or too small");
     if (!counts || !status) return fail(XM_ERR_INVALID, "counts/status buffers are NULL");
     if (o && o->flags != 0) return fail(XM_ERR_INVALID, "unknown xm_count_opts flag");
@@ -322,7 +360,7 @@ int enqueue_count(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const*
     a.split_items = reinterpret_cast<uint4*>(base + L.off_split);
     a.split_cap = L.split_cap;
     a.don = reinterpret_cast<uint32_t*>(base + L.off_don);
-    a.don_cap = xm::kDonCap;
+    a.don_cap = L.don_cap;
     for (uint32_t q = 0; q <= xm::kQueues; q++) a.qbase[q] = L.qbase[q];
     a.roots = (o && o->roots_dev) ? o->roots_dev : nullptr;
     a.n_src = a.roots ? o->n_roots : g->n;
@@ -345,7 +383,29 @@ int enqueue_count(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const*
     a.list_cap = listing ? o->list_cap : 0;
 
     std::vector<xm::InitArgs> inits;
-    for (uint32_t first = 0; first < n_plans; first += xm::kMaxPlansPerInit) {
+    if (on_static) {
+        // descriptors travel in kernel arguments: no device copy of a plan is
+        // allocated; one set-up launch clears the control words
+        PlanDesc* table = reinterpret_cast<PlanDesc*>(base + L.off_table);
+        for (uint32_t i = 0; i < n_plans; i++) {
+            hipError_t e = xm::copy_desc(table + i, plans[i]->desc, stream);
+            if (e != hipSuccess) return hip_fail(e, "descriptor copy launch");
+        }
+        xm::InitArgs ia;
+        std::memset(&ia, 0, sizeof(ia));
+        ia.table = table;
+        ia.count = 0;
+        ia.n_plans = n_plans;
+        ia.zero_ctl = 1;
+        ia.ctl = a.ctl;
+        ia.plan_flags = a.plan_flags;
+        ia.counts = a.counts;
+        ia.don = a.don;
+        ia.don_cap = a.don_cap;
+        ia.list_count = a.list_count;
+        inits.push_back(ia);
+    }
+    for (uint32_t first = 0; first < n_plans && !on_static; first += xm::kMaxPlansPerInit) {
         xm::InitArgs ia;
         std::memset(&ia, 0, sizeof(ia));
         ia.table = reinterpret_cast<PlanDesc*>(base + L.off_table);
@@ -855,6 +915,12 @@ int xm_count(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* plan
              void* workspace, size_t ws_bytes, uint64_t* counts_dev, int32_t* status_dev, void* hip_stream) {
     return enqueue_count(g, n_plans, plans, opts, workspace, ws_bytes, counts_dev, status_dev,
                          static_cast<hipStream_t>(hip_stream));
+}
+
+int xm_count_static(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* plans,
+                    const xm_count_opts* opts, uint64_t* counts_dev, int32_t* status_dev, void* hip_stream) {
+    return enqueue_count(g, n_plans, plans, opts, nullptr, 0, counts_dev, status_dev,
+                         static_cast<hipStream_t>(hip_stream), true);
 }
 
 int xm_count_capture(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* plans,
