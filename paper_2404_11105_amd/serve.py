@@ -17,7 +17,10 @@ still queued is completed with status XM_ERR_CANCELLED without running.
 A request may be anchored: pin = (v, x) counts only the embeddings that map
 pattern vertex v to data node x (a constant pattern vertex).  Its plan starts
 at v and its launch is restricted to the root subset {x}; anchored requests
-batch with others on the same graph and node.
+batch with others on the same graph and node.  A request may also carry a
+root subset, roots = (v, nodes): the embeddings that map v into `nodes` (an
+exact partial count); it batches with requests on the same graph and the
+same node array.
 
 Order: policy "fifo" takes the oldest pending request first; policy "sjf"
 takes the request with the smallest estimated cost first (the backend's
@@ -50,6 +53,7 @@ class Request:
     deadline: float | None
     future: Future
     pin: tuple | None = None      # (pattern vertex, data node)
+    roots: tuple | None = None    # (pattern vertex, uint32 node array)
     done: float = 0.0
     status: int = 0
     count: int | None = None
@@ -103,10 +107,11 @@ class GpuBackend:
     def new_slot(self):
         return self.torch.cuda.Stream()
 
-    def launch(self, slot, graph_id, plans, node=None):
+    def launch(self, slot, graph_id, plans, node=None, roots=None):
         import numpy as np
         from .api import Counter
-        roots = None if node is None else np.array([node], dtype=np.uint32)
+        if roots is None and node is not None:
+            roots = np.array([node], dtype=np.uint32)
         c = Counter(self.graphs[graph_id], plans, roots=roots, **self.opts)
         c.run(slot)
         ev = self.torch.cuda.Event()
@@ -147,15 +152,20 @@ class Server:
         self.thread.start()
 
     # ---- client side
-    def submit(self, graph_id, pattern, deadline_s: float | None = None, pin=None) -> Future:
+    def submit(self, graph_id, pattern, deadline_s: float | None = None, pin=None, roots=None) -> Future:
         """Queue a count of `pattern` on graph `graph_id`; pin = (v, x) anchors
-        pattern vertex v at data node x.  The future gives (count, status)."""
+        pattern vertex v at data node x; roots = (v, nodes) counts only the
+        embeddings that map v into the uint32 array `nodes`.  The future
+        gives (count, status)."""
+        if pin is not None and roots is not None:
+            raise ValueError("a request takes pin or roots, not both")
         now = time.perf_counter()
         f = Future()
         with self.lock:
             r = Request(self.next_id, graph_id, pattern, now,
                         now + deadline_s if deadline_s is not None else None, f,
-                        pin=tuple(pin) if pin is not None else None)
+                        pin=tuple(pin) if pin is not None else None,
+                        roots=(int(roots[0]), roots[1]) if roots is not None else None)
             self.next_id += 1
             self.pending.append(r)
             self.lock.notify()
@@ -184,6 +194,17 @@ class Server:
         r.count = count
         self.completed.append(r)
         r.future.set_result((count, status))
+
+    @staticmethod
+    def _vertex(r):
+        """The pattern vertex a request fixes the start of its plan at."""
+        return r.pin[0] if r.pin else (r.roots[0] if r.roots else None)
+
+    @staticmethod
+    def _target(r):
+        """Requests batch together only with the same anchor node or the
+        same root array."""
+        return ("pin", r.pin[1]) if r.pin else (("roots", id(r.roots[1])) if r.roots else None)
 
     @staticmethod
     def _code(exc) -> int:
@@ -218,7 +239,7 @@ class Server:
             def est(r):
                 # a request that cannot be planned sorts last and fails below
                 try:
-                    return self.backend.cost(r.graph_id, r.pattern, r.pin[0] if r.pin else None)
+                    return self.backend.cost(r.graph_id, r.pattern, self._vertex(r))
                 except Exception:
                     return float("inf")
             if sjf and now - head.submitted <= self.age_s:
@@ -230,13 +251,14 @@ class Server:
             # order; under sjf only those within 8x of the head's cost, so a
             # light launch is not held up by a heavy plan in it
             node = head.pin[1] if head.pin else None
+            roots = head.roots[1] if head.roots else None
+            target = self._target(head)
             head_est = est(head) if sjf else 0.0
             batch, rest = [], collections.deque()
             while self.pending:
                 r = self.pending.popleft()
-                r_node = r.pin[1] if r.pin else None
                 similar = not sjf or r is head or (head_est / 8 <= est(r) <= head_est * 8)
-                if r.graph_id == head.graph_id and r_node == node and len(batch) < self.max_batch and similar and (
+                if r.graph_id == head.graph_id and self._target(r) == target and len(batch) < self.max_batch and similar and (
                         r.deadline is None or now <= r.deadline):
                     batch.append(r)
                 else:
@@ -245,7 +267,7 @@ class Server:
             plans, ok = [], []
             for r in batch:
                 try:
-                    plans.append(self.backend.plan(r.graph_id, r.pattern, r.pin[0] if r.pin else None))
+                    plans.append(self.backend.plan(r.graph_id, r.pattern, self._vertex(r)))
                     ok.append(r)
                 except Exception as exc:
                     self._finish(r, self._code(exc), None)
@@ -277,7 +299,8 @@ class Server:
             self.pending = collections.deque(sorted(rest, key=lambda q: q.rid))
             si = free[0]
             try:
-                handle = self.backend.launch(self.slots[si], head.graph_id, plans, node)
+                handle = (self.backend.launch(self.slots[si], head.graph_id, plans, node) if roots is None
+                          else self.backend.launch(self.slots[si], head.graph_id, plans, roots=roots))
             except Exception as exc:
                 for r in batch:
                     self._finish(r, self._code(exc), None)

@@ -96,6 +96,135 @@ def rmat20_subset():
                              "m": g.m, "results": res})
 
 
+def _per_root(g, pat, roots, root_vertex, workers):
+    """Oracle counts of one pattern per root, one root per oracle call, the
+    calls spread over `workers` host threads (the oracle runs single-threaded
+    per call and releases the interpreter while it counts)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(r):
+        t = time.time()
+        c = oracle.count(g, pat, roots=np.array([r], dtype=np.uint32), root_vertex=root_vertex, mode="B")
+        print(pat.name, int(r), c, round(time.time() - t, 1), flush=True)
+        return str(c), round(time.time() - t, 1)
+
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        res = list(ex.map(one, [int(r) for r in roots]))
+    return [c for c, _ in res], [s for _, s in res]
+
+
+def rmat20_hubs():
+    """Per-root oracle counts on R-MAT scale 20 hub roots (generated ids).
+
+    tt4p: the 16 nodes of largest total degree (ranks 0-15, degree ~31K-40K);
+    the oracle takes 20-60 minutes per such root.  c5chord enumerates three
+    levels below its start vertex in the oracle's order: a root of degree
+    ~450 (rank ~8,000) already takes ~4 minutes, one of rank 4,000 (degree
+    ~1,300) did not finish in 25 minutes; it gets the eight roots of ranks
+    8000-8007, the highest-ranked ones within a budget of ~5 minutes each."""
+    g = xmgen.rmat(20, seed=0)
+    deg = g.out_deg() + g.in_deg()
+    order = np.argsort(-deg, kind="stable")
+    res = {}
+    for name, ranks in [("c5chord", range(8000, 8008)), ("tt4p", range(0, 16))]:
+        roots = order[list(ranks)].astype(np.uint32)
+        t = time.time()
+        counts, secs = _per_root(g, xmgen.named(name), roots, 0, THREADS)
+        res[name] = {"root_vertex": 0, "ranks": list(ranks), "roots": roots.tolist(),
+                     "degrees": deg[roots].tolist(), "counts": counts, "seconds": secs,
+                     "wall_seconds": round(time.time() - t, 1)}
+        _write("rmat20_hubs", {"graph": "rmat(scale=20, edge_factor=16, abcd=(.57,.19,.19,.05), seed=0)",
+                               "m": g.m, "mode": "B (last vertex with one constraint counted from |L|)",
+                               "threads": THREADS, "results": res})
+
+
+def batch_subsets(workers=None):
+    """Root-subset parity for 16 of the 256 batch patterns on R-MAT scale 22:
+    per size 3-6 the two with the longest plain launch and two seeded others.
+    Each is counted on roots of its own root share (the roots the batch
+    counts): the two of largest degree in the share and 30 seeded others,
+    mapped back to the generated ids; one oracle count per root."""
+    from paper_2404_11105_amd import workloads
+    rec = json.load(open(workloads.BATCH_PATH))
+    acc = rec["accepted"]
+    rng = np.random.default_rng(256)
+    pick = []
+    for k in (3, 4, 5, 6):
+        idx = [i for i, e in enumerate(acc) if e["k"] == k]
+        heavy = sorted(idx, key=lambda i: -acc[i]["plain_ms"])[:2]
+        rest = [i for i in idx if i not in heavy]
+        pick += heavy + [int(x) for x in rng.choice(rest, size=2, replace=False)]
+    g = workloads.batch_graph()
+    new_of_old = workloads.degree_order(g)
+    old_of_new = np.empty_like(new_of_old)
+    old_of_new[new_of_old] = np.arange(g.n, dtype=np.uint32)
+    pats = workloads.batch_patterns()
+    out = []
+    for i in pick:
+        e = acc[i]
+        share = workloads.share_roots(g.n, e["share"])
+        stored = np.concatenate([share[:2], np.sort(rng.choice(share[2:], size=30, replace=False))])
+        roots = old_of_new[stored]
+        from paper_2404_11105_amd.api import Plan
+        rv = Plan(pats[i], reduced=True, symmetry=e["symmetry"], root_share=e["share"]).describe()["root_vertex"]
+        t = time.time()
+        counts, secs = _per_root(g, pats[i], roots, rv, workers or THREADS)
+        out.append({"index": i, "k": e["k"], "seed": e["seed"], "share": e["share"], "symmetry": e["symmetry"],
+                    "plain_ms": e["plain_ms"], "root_vertex": rv, "stored_roots": stored.tolist(),
+                    "roots": roots.tolist(), "counts": counts, "oracle_seconds": round(sum(secs), 1),
+                    "wall_seconds": round(time.time() - t, 1)})
+        print("pattern", i, e["k"], e["share"], sum(int(c) for c in counts), out[-1]["wall_seconds"], flush=True)
+        _write("batch256_subsets", {"graph": "rmat(scale=22, edge_factor=16, abcd=(.57,.19,.19,.05), seed=0)",
+                                    "m": g.m, "mode": "B", "patterns": out})
+
+
+SERVE_REQUESTS = [  # (R-MAT scale, seed, pattern): one request per serving graph
+    (18, 0, "p7hub"), (19, 1, "rand6"), (20, 2, "c5chord"), (21, 3, "rand5"),
+    (22, 4, "bifan"), (23, 5, "rand4"), (24, 6, "ffl"), (24, 7, "c4"),
+]
+
+
+def serve_pattern(name):
+    return {"rand6": lambda: xmgen.random_pattern(6, 777), "rand5": lambda: xmgen.random_pattern(5, 555),
+            "rand4": lambda: xmgen.random_pattern(4, 444)}.get(name, lambda: xmgen.named(name))()
+
+
+def serve_roots(g, seed, hubs: bool):
+    """64 roots in the generated ids: with hubs, degree ranks 1000-1003 (lists
+    of hundreds to thousands of arcs) and 60 seeded nodes below degree rank
+    10,000; without, 64 seeded nodes below degree rank 50,000 (the oracle
+    enumerates every level but the last one, which is out of its reach on the
+    largest hubs, and for patterns of 5 or more vertices on any hub)."""
+    deg = g.out_deg() + g.in_deg()
+    order = np.argsort(-deg, kind="stable")
+    rng = np.random.default_rng(1000 + seed)
+    if not hubs:
+        # below the 50,000 largest: generator ids are skewed, low ids are hubs
+        return np.sort(rng.choice(order[50000:], size=64, replace=False)).astype(np.uint32)
+    uni = rng.choice(order[10000:], size=60, replace=False)
+    return np.unique(np.concatenate([order[1000:1004], uni])).astype(np.uint32)
+
+
+def serve_scales():
+    """Per-root oracle counts of one request per serving graph (R-MAT scales
+    18-24, 16 arcs per node, seeds 0-7), start vertex 0, on 64 roots each
+    (with four hubs for the patterns of at most 4 vertices)."""
+    out = []
+    for scale, seed, name in SERVE_REQUESTS:
+        t = time.time()
+        g = xmgen.rmat(scale, seed=seed)
+        pat = serve_pattern(name)
+        roots = serve_roots(g, seed, hubs=pat.k <= 4)
+        counts, secs = _per_root(g, pat, roots, 0, THREADS)
+        out.append({"scale": scale, "seed": seed, "pattern": name, "arcs": [list(a) for a in pat.arcs],
+                    "k": pat.k, "m": g.m, "root_vertex": 0, "roots": roots.tolist(), "counts": counts,
+                    "oracle_seconds": round(sum(secs), 1), "wall_seconds": round(time.time() - t, 1)})
+        print(scale, name, sum(int(c) for c in counts), out[-1]["wall_seconds"], flush=True)
+        del g
+        _write("serve_scales", {"recipe": "rmat(scale, edge_factor=16, abcd=(.57,.19,.19,.05), seed)",
+                                "mode": "B", "requests": out})
+
+
 if __name__ == "__main__":
     for name in sys.argv[1:] or ["cases", "uniform2000", "rmat16", "rmat20_subset"]:
         globals()[name]()

@@ -117,6 +117,62 @@ def test_rmat20_root_subset_parity(xa):
             assert st == [0] and got == [int(r["count"])], (name, reduced)
 
 
+def test_rmat20_hub_roots_per_root_parity(xa):
+    """R-MAT scale 20 hub roots, compared one root at a time: tt4p on the 16
+    nodes of largest degree (their first-level lists are split into stolen
+    sub-ranges), c5chord on the degree ranks 8000-8007 (the highest ranks
+    the oracle finishes within its budget), reduced and unreduced plans."""
+    path = os.path.join(HERE, "golden", "rmat20_hubs.json")
+    gold = json.load(open(path))
+    g = xmgen.rmat(20, seed=0)
+    assert g.m == gold["m"]
+    G = xa.Graph(g)
+    wd = xa.Watchdog()
+    for name, r in gold["results"].items():
+        for reduced in (True, False):
+            p = xa.Plan(xmgen.named(name), reduced=reduced, graph=G, root_vertex=r["root_vertex"])
+            for root, want in zip(r["roots"], r["counts"]):
+                banner(f"  {name} reduced={reduced} root {root}")
+                c = xa.Counter(G, [p], roots=np.array([root], dtype=np.uint32), cancel=wd)
+                wd.arm(60.0)
+                c.run()
+                got, st = c.results()
+                wd.disarm()
+                assert st == [0] and got == [int(want)], (name, reduced, root)
+
+
+def test_serving_one_request_per_graph_scale_vs_oracle(xa):
+    """Config 5's graphs (R-MAT scales 18-24 and 24, seeds 0-7, all resident
+    at once): one root-subset request per graph through the serving loop,
+    each count equal to the oracle's sum over its 64 roots (for the patterns
+    of at most 4 vertices, 4 hubs of degree rank 1000-1003 among them)."""
+    from paper_2404_11105_amd.serve import GpuBackend, Server
+    sys_path = os.path.join(HERE, "golden")
+    import sys
+    if sys_path not in sys.path:
+        sys.path.insert(0, sys_path)
+    from make_golden import serve_pattern
+    gold = json.load(open(os.path.join(HERE, "golden", "serve_scales.json")))["requests"]
+    graphs = {}
+    for i, req in enumerate(gold):
+        banner(f"serving graph {i}: R-MAT scale {req['scale']} seed {req['seed']}")
+        g = xmgen.rmat(req["scale"], seed=req["seed"])
+        assert g.m == req["m"]
+        graphs[i] = xa.Graph(g, dense_rows=2 << 30)
+        del g
+    srv = Server(GpuBackend(graphs), 64 << 30, slots=4, max_batch=8)
+    futs = []
+    for i, req in enumerate(gold):
+        pat = serve_pattern(req["pattern"])
+        assert [list(a) for a in pat.arcs] == req["arcs"]
+        futs.append(srv.submit(i, pat, roots=(req["root_vertex"], np.array(req["roots"], dtype=np.uint32))))
+    res = [f.result(timeout=300) for f in futs]
+    srv.close()
+    for req, (c, st) in zip(gold, res):
+        banner(f"  scale {req['scale']} {req['pattern']}: {c}")
+        assert st == 0 and c == sum(int(x) for x in req["counts"]), req["scale"]
+
+
 def test_watchdog_flag_in_pinned_host_memory(xa):
     import time
     banner("watchdog: pinned host cancel flag raised before the launch, then cleared")
@@ -184,3 +240,38 @@ def test_side_stream_launch_waits_for_setup(xa):
         torch.cuda.synchronize()
         counts, status = c.results()
         assert status == [0, 0] and counts == want
+
+
+def test_batch256_root_subset_parity(xa):
+    """Config 4's graph (R-MAT scale 22) and 16 of its 256 patterns (per size
+    3-6 the two with the longest plain launch and two others): each counted
+    one root at a time on roots of its own root share -- the two of largest
+    degree in the share and 30 others -- with the plan the batch uses
+    (reduced, symmetry broken on the stored side, here with its start vertex
+    fixed so per-root counts stay exact), against the oracle."""
+    from paper_2404_11105_amd import workloads
+    gold = json.load(open(os.path.join(HERE, "golden", "batch256_subsets.json")))
+    banner("R-MAT scale 22 (generated ids) for batch256 root-subset parity")
+    g = workloads.batch_graph()
+    assert g.m == gold["m"]
+    G = xa.Graph(g)
+    del g
+    pats = workloads.batch_patterns()
+    accepted = json.load(open(workloads.BATCH_PATH))["accepted"]
+    wd = xa.Watchdog()
+    for r in gold["patterns"]:
+        pat = pats[r["index"]]
+        assert (pat.k, r["seed"], r["share"]) == (r["k"], accepted[r["index"]]["seed"], accepted[r["index"]]["share"])
+        p = xa.Plan(pat, reduced=True, graph=G, root_vertex=r["root_vertex"], symmetry=r["symmetry"])
+        banner(f"  pattern {r['index']} (k={r['k']}, share {r['share']}): {len(r['roots'])} roots")
+        roots = np.array(r["roots"], dtype=np.uint32)
+        c = xa.Counter(G, [p], roots=roots, cancel=wd)
+        wd.arm(120.0)
+        c.run()
+        got, st = c.results()
+        wd.disarm()
+        assert st == [0] and got == [sum(int(x) for x in r["counts"])], r["index"]
+        for root, want in zip(r["roots"][:2], r["counts"][:2]):  # the share's two largest hubs alone
+            c = xa.Counter(G, [p], roots=np.array([root], dtype=np.uint32))
+            c.run()
+            assert c.results()[0] == [int(want)], (r["index"], root)

@@ -34,9 +34,11 @@ class FakeBackend:
     def new_slot(self):
         return object()
 
-    def launch(self, slot, graph_id, plans, node=None):
+    def launch(self, slot, graph_id, plans, node=None, roots=None):
         g = self.graphs[graph_id]
-        if node is None:
+        if roots is not None:
+            counts = [oracle.count(g, p, roots=roots, root_vertex=v) for p, v in plans]
+        elif node is None:
             counts = [oracle.count(g, p) for p, _ in plans]
         else:
             counts = [oracle.count(g, p, roots=[node], root_vertex=v) for p, v in plans]
@@ -195,10 +197,10 @@ class FailingBackend(FakeBackend):
             raise MemoryError("workspace sizing failed")
         return super().footprint(graph_id, plans, node)
 
-    def launch(self, slot, graph_id, plans, node=None):
+    def launch(self, slot, graph_id, plans, node=None, roots=None):
         if any(p.name == "c3" for p, _ in plans):
             raise RuntimeError("launch failed")
-        return super().launch(slot, graph_id, plans, node)
+        return super().launch(slot, graph_id, plans, node, roots)
 
 
 @pytest.mark.parametrize("policy", ["fifo", "sjf"])
@@ -225,3 +227,24 @@ def test_backend_errors_fail_their_requests_and_keep_serving(policy):
     # every request on graph "r" shares a batch whose sizing raised, unless
     # it ran alone; none of them hangs
     assert all(s in (0, -10) for (gid, _), (_, s) in zip(reqs, res) if gid == "r")
+
+
+def test_root_subset_requests_batch_by_array_and_are_exact():
+    """Requests with a root subset (v, nodes) count the embeddings that map
+    v into nodes; they batch only with requests on the same array, and the
+    counts are the oracle's partial sums."""
+    import numpy as np
+    gs = graphs()
+    be = FakeBackend(gs, secs_per_plan=0.001)
+    srv = Server(be, hbm_budget=10_000, slots=2, max_batch=8)
+    a = np.arange(0, 200, 7, dtype=np.uint32)
+    b = np.arange(3, 200, 11, dtype=np.uint32)
+    reqs = [(xmgen.named(n), (0, a)) for n in ["ffl", "c3", "bifan"]] + [(xmgen.named("c4"), (1, b)),
+                                                                          (xmgen.named("path3"), (0, b))]
+    futs = [srv.submit("u", p, roots=r) for p, r in reqs]
+    res = [f.result(timeout=30) for f in futs]
+    srv.close()
+    for (p, (v, nodes)), (c, s) in zip(reqs, res):
+        assert s == 0 and c == oracle.count(gs["u"], p, roots=nodes, root_vertex=v)
+    # the three requests on array a went out together at most in one launch each way
+    assert srv.launches <= 4
