@@ -1,18 +1,27 @@
 #!/usr/bin/env python3
 """Benchmark: exact directed-pattern counting on one MI355X.
 
-Workload (default): R-MAT scale 16 (65,536 nodes, ~955K arcs after removing
-repeats and loops, (a,b,c,d) = (.57,.19,.19,.05), seed 0), uint32 out+in CSR
-resident in HBM, and four patterns: feed-forward triangle, directed 3-cycle,
-bi-fan, directed 4-cycle.  The graph is stored with its nodes renumbered by
-decreasing degree (load time, untimed).  One step counts all four with their
-reduced, symmetry-broken plans (one embedding per automorphism orbit, scaled
-by the orbit size: the same labelled counts) in one persistent launch,
-replayed as a HIP graph.  The same step is also timed without symmetry
-breaking, as plain per-pattern launches and with unreduced plans.
+Default workload (one JSON line, the repository's benchmark contract): one
+resident R-MAT scale 22 graph (4,194,304 nodes, ~65.2M arcs after removing
+repeats and loops, (a,b,c,d) = (.57,.19,.19,.05), seed 0; uint32 out+in CSR,
+stored with its nodes renumbered by decreasing degree at load, untimed) and
+256 seeded random connected directed patterns of 3-6 vertices, 64 of each
+size, each counted on its root share (paper_2404_11105_amd/workloads.py).
+One step is ONE persistent launch that counts all 256 reduced,
+symmetry-broken plans, replayed as a HIP graph with launch options tuned
+offline (workloads/batch256_tuned.json).  The same 256 plans are also timed
+as 256 plain launches (batched vs plain), and every count must agree.
 
-Prints one JSON line (see the repository's benchmark contract).  Only the
-`cpu_baseline` leg calls the oracle, on a bounded root sample.
+Also in the line: the roofline of the count kernel (issued bytes from the
+host walk stored in workloads/batch256_traffic.json, measured HBM traffic
+and VALU issue from the rocprofv3 summaries under profiles/ when they were
+taken on this build), the oracle's throughput on a bounded sample of the
+same workload (1 core and all cores, 1 warm-up then the median of 5), and
+two smaller workloads as extra keys: R-MAT scale 16 with the four motifs
+(batched, plain, unreduced) and R-MAT scale 20 with the two 5-vertex
+patterns, reduced vs unreduced plans.
+
+Only the `cpu_baseline` leg calls the oracle.
 """
 from __future__ import annotations
 
@@ -29,7 +38,10 @@ sys.path.insert(0, ROOT)
 METRIC = ("embeddings counted/sec + adjacency elems intersected/s (HBM GB/s %), "
           "batched vs plain")
 HBM_PEAK_GBPS = 8000.0
+N_CU, CLOCK_HZ = 256, 2.4e9   # MI355X: VALU issue capacity = one wave64 instruction per CU per cycle
 PATTERNS = ["ffl", "c3", "bifan", "c4"]
+C5CHORD_SHARE = 6             # scale-20 extra: the 5-cycle with a chord on 1/64 of the roots
+WL_DIR = os.path.join(ROOT, "paper_2404_11105_amd", "workloads")
 
 
 def log(*a):
@@ -94,47 +106,99 @@ def timed_plain(counters, stream, steps, warmup, progress=None):
     return (time.perf_counter() - t0) / steps * 1e3
 
 
-def cpu_baseline(g, pats, target_s=4.0):
-    """The oracle as it stands, on a seeded uniform sample of roots."""
-    import numpy as np
+def host_cores() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def oracle_timing(g, work, threads, reps=5):
+    """The oracle as it stands on `work` = [(pattern, roots, root_vertex)]:
+    one warm-up pass, then the median of `reps` timed passes (embeddings,
+    seconds).  With threads > 1 the work items run concurrently, one oracle
+    call per item on its own host thread (the oracle's own threads split a
+    call's roots 64 at a time, too coarse for these samples)."""
+    from concurrent.futures import ThreadPoolExecutor
 
     import oracle
-    try:
-        cores = len(os.sched_getaffinity(0))
-    except AttributeError:
-        cores = os.cpu_count() or 1
-    threads = max(1, min(16, cores))
-    rng = np.random.default_rng(12345)
-    total_c, total_t, parts = 0, 0.0, []
-    for p in pats:
-        frac = 0.002
-        while True:
-            k = max(1, int(frac * g.n))
-            roots = np.sort(rng.choice(g.n, size=k, replace=False)).astype(np.uint32)
-            t = time.perf_counter()
-            c = oracle.count(g, p, roots=roots, threads=threads)
-            dt = time.perf_counter() - t
-            if dt >= target_s / 4 or frac >= 1.0:
-                break
-            frac = min(1.0, frac * max(2.0, min(50.0, target_s / max(dt, 1e-3))))
-        total_c += c
-        total_t += dt
-        parts.append(f"{p.name}:{k}/{g.n} roots")
-    return {"value": total_c / total_t, "unit": "embeddings/s", "cores": threads, "kind": "oracle",
-            "sample": "seeded uniform root samples per pattern (" + ", ".join(parts) +
-                      f"), {total_c} embeddings in {total_t:.2f} s"}
+
+    def item(w):
+        p, r, rv = w
+        return oracle.count(g, p, roots=r, root_vertex=rv, mode="B")
+
+    def one():
+        t = time.perf_counter()
+        if threads == 1:
+            c = sum(item(w) for w in work)
+        else:
+            with ThreadPoolExecutor(max_workers=threads) as ex:
+                c = sum(ex.map(item, work))
+        return c, time.perf_counter() - t
+
+    one()
+    runs = sorted((one() for _ in range(reps)), key=lambda x: x[1])
+    return runs[len(runs) // 2]
 
 
-def traffic_from_profile(workload):
-    path = os.path.join(ROOT, "profiles", "count_kernel_rmat16_traffic.json")
+def cpu_baseline(g, work, sample_desc):
+    """1 core and all T cores, each 1 warm-up + median of 5; `value` is the
+    all-core rate (embeddings/s), the 1-core rate is beside it."""
+    T = host_cores()
+    c1, t1 = oracle_timing(g, work, 1)
+    cT, tT = oracle_timing(g, work, T)
+    assert c1 == cT
+    return {"value": cT / tT, "unit": "embeddings/s", "cores": T, "kind": "oracle",
+            "sample": sample_desc + f"; {cT} embeddings; median of 5 after 1 warm-up: {tT:.3f} s on {T} "
+                                    f"threads, {t1:.3f} s on 1",
+            "value_1core": c1 / t1, "seconds_1core": round(t1, 4), "seconds_all_cores": round(tT, 4)}
+
+
+def write_cpu_sample(n_patterns=16, per_pattern=64, chunks=4):
+    """The oracle's sample of the batch workload (stored in
+    workloads/batch256_cpu_sample.json; chosen from the stored batch without
+    running anything): every 16th pattern (four of each size) on 64 roots of
+    its own root share of degree rank [n/64, n/16) (lists of tens of arcs: the
+    bulk of the roots a launch walks; hubs are out of the oracle's reach in
+    seconds), in the generated ids, split into 4 work items per pattern."""
+    import numpy as np
+
+    from paper_2404_11105_amd import workloads
+    rec = json.load(open(workloads.BATCH_PATH))["accepted"]
+    g = workloads.batch_graph()
+    new_of_old = workloads.degree_order(g)
+    old_of_new = np.empty_like(new_of_old)
+    old_of_new[new_of_old] = np.arange(g.n, dtype=np.uint32)
+    rng = np.random.default_rng(64)
+    plans = workloads.batch_plans()
+    work = []
+    for i in range(0, len(rec), len(rec) // n_patterns):
+        sh = workloads.share_roots(g.n, rec[i]["share"])
+        sh = sh[(sh >= g.n // 64) & (sh < g.n // 16)]
+        roots = np.sort(old_of_new[rng.choice(sh, size=per_pattern, replace=False)])
+        rv = plans[i].describe()["root_vertex"]
+        for c in np.array_split(roots, chunks):
+            work.append([i, c.tolist(), rv])
+    desc = (f"{n_patterns} of the 256 patterns (every 16th), {per_pattern} roots each from its root share at "
+            f"degree ranks [n/64, n/16), generated ids, {chunks} work items per pattern")
+    out = {"description": desc, "work": work}
+    with open(os.path.join(WL_DIR, "batch256_cpu_sample.json"), "w") as f:
+        json.dump(out, f)
+        f.write("\n")
+    return out
+
+
+def profile_record(name, workload_id):
+    """A counter summary under profiles/ taken on this library build and
+    workload, else None."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     try:
         rec = json.load(open(path))
-        # counters of this build and this workload only
-        if rec.get("lib_sha256_16") != lib_hash() or rec.get("workload_id") != workload:
+        if rec.get("lib_sha256_16") != lib_hash() or rec.get("workload_id") != workload_id:
             return None
-        return rec.get("hbm_bytes_per_launch")
+        return rec
     except Exception:
         return None
 
@@ -153,103 +217,205 @@ def copy_probe(mib: int, reps: int):
     print(json.dumps({"copy_probe_bytes": n * 4, "reps": reps}), flush=True)
 
 
+def load_json(name):
+    path = os.path.join(WL_DIR, name)
+    return json.load(open(path)) if os.path.exists(path) else None
+
+
+def batch_setup():
+    """The scale-22 graph (degree order, dense rows), its 256 plans on their
+    root shares, and the stored launch options."""
+    from paper_2404_11105_amd import Graph, workloads
+    log("[batch] generating R-MAT scale 22")
+    t = time.time()
+    g = workloads.batch_graph()
+    log(f"[batch]   {time.time() - t:.1f} s; loading in degree order with dense rows")
+    t = time.time()
+    G = Graph(g, order_by_degree=True, dense_rows=workloads.ROW_BYTES)
+    log(f"[batch]   {time.time() - t:.1f} s, rows {G.dense_rows_info()}")
+    pats = workloads.batch_patterns()
+    shares = workloads.batch_shares()
+    t = time.time()
+    plans = workloads.batch_plans()
+    t_plan = time.time() - t
+    tuned = load_json("batch256_tuned.json") or {"opts": {}}
+    return g, G, pats, shares, plans, t_plan, tuned
+
+
 def bench_batch256(args):
-    """256 capped random patterns on one resident R-MAT scale 22 graph: one
-    persistent batched launch (HIP graph, autotuned) against 256 plain
-    launches of the same plans; batched == plain for every count, and oracle
-    root-subset parity on a sample of patterns."""
+    """The contract line: one persistent launch of 256 plans against 256
+    plain launches on the resident scale-22 graph."""
     import numpy as np
     import torch
 
-    import oracle
-    from paper_2404_11105_amd import Counter, Graph, Plan, workloads
+    from paper_2404_11105_amd import Counter, workloads
     from paper_2404_11105_amd.api import workspace_bytes
-    from paper_2404_11105_amd.tune import tune
 
     torch.cuda.set_device(0)
-    log("[batch] generating R-MAT scale 22")
-    g = workloads.batch_graph()
-    pats = workloads.batch_patterns()
-    order = not args.generated_order
-    log("[batch] loading" + (" (nodes in degree order)" if order else ""))
-    G = Graph(g, order_by_degree=order)
-    sym = not args.no_symmetry
-    log("[batch] planning" + (" (symmetry directions from a sampled host walk)" if sym else ""))
-    t_plan = time.time()
-    plans = [Plan(p, reduced=True, graph=G, symmetry=sym) for p in pats]
-    t_plan = time.time() - t_plan
+    g, G, pats, shares, plans, t_plan, tuned = batch_setup()
+    opts = dict(tuned["opts"])
+    row_min = G.dense_rows_info()["row_min"]
+    key = workloads.plans_key(plans, row_min)
     n_sym = sum(1 for p in plans if p.describe()["sym_mult"] > 1)
-    log(f"[batch] {n_sym} plans with symmetry breaking, planned in {t_plan:.1f} s")
+    log(f"[batch] 256 plans in {t_plan:.1f} s ({n_sym} symmetry-broken), options {opts}")
     s = torch.cuda.Stream()
-    log("[batch] autotuning")
-    rows_info = G.dense_rows_info()
-    log(f"[batch] dense rows {rows_info}")
-    opts, trec = tune(G, plans, stream=s, reps=1, budget_s=120, log=log)
-    log(f"[batch] tuned {opts} ({trec['ms']:.1f} ms vs default {trec['default_ms']:.1f} ms)")
     cb = Counter(G, plans, **opts)
     cb.capture(s)
-    log("[batch] batched launches (HIP graph)")
+    log("[batch] batched launches (HIP graph replays)")
     ms_b, gpu_b = timed_steps(cb, s, args.steps, args.warmup, progress=log)
     counts, status = cb.results()
     assert all(x == 0 for x in status), status
-    log("[batch] 256 plain launches")
-    ws = torch.empty(max(workspace_bytes(G, [p], **opts) for p in plans), dtype=torch.uint8,
-                     device="cuda")
-    plain = [Counter(G, [p], workspace=ws, **opts) for p in plans]
-    steps_plain = max(1, args.steps // 2)
-    ms_p = timed_plain(plain, s, steps_plain, 1, progress=log)
-    plain_counts = [c.results()[0][0] for c in plain]
-    assert plain_counts == counts, "batched and plain counts differ"
-    ms_nosym = None
-    if sym and n_sym:
-        # every embedding enumerated: the same counts
-        log("[batch] batched launch without symmetry breaking")
-        cn = Counter(G, [Plan(p, reduced=True, graph=G) for p in pats], **opts)
-        cn.capture(s)
-        ms_nosym, _ = timed_steps(cn, s, 1, 1, progress=log)
-        assert cn.results()[0] == counts, "symmetry-broken and plain plans differ"
-        del cn
-    # oracle parity on root subsets of a sample of patterns (plans without
-    # symmetry breaking on the graph in its generated order: a subset count
-    # is per root, in the caller's node ids)
-    log("[batch] oracle root-subset parity")
-    del cb, plain, ws
-    if order:
-        G = Graph(g)
-    rng = np.random.default_rng(7)
-    sample_ids = rng.choice(len(pats), size=12, replace=False)
-    threads = max(1, min(16, len(os.sched_getaffinity(0))))
-    parity = True
-    for i in sample_ids:
-        roots = np.sort(rng.choice(g.n, size=256, replace=False)).astype(np.uint32)
-        pi = Plan(pats[i], reduced=True, graph=G)
-        c = Counter(G, [pi], roots=roots, **opts)
-        c.run(s)
-        s.synchronize()
-        got = c.results()[0][0]
-        want = oracle.count(g, pats[i], roots=roots, root_vertex=pi.root_vertex,
-                            threads=threads, mode="B")
-        parity = parity and got == want
+    extras = {}
+    if not args.no_extras:
+        log("[batch] 256 plain launches")
+        ws = torch.empty(max(workspace_bytes(G, [p], **opts) for p in plans), dtype=torch.uint8, device="cuda")
+        plain = [Counter(G, [p], workspace=ws, **opts) for p in plans]
+        steps_plain = max(1, args.steps // 4)
+        ms_p = timed_plain(plain, s, steps_plain, 1, progress=log)
+        plain_counts = [c.results()[0][0] for c in plain]
+        assert plain_counts == counts, "batched and plain counts differ"
+        extras.update({"plain_ms_per_step": round(ms_p, 3), "plain_steps": steps_plain,
+                       "batched_vs_plain_speedup": round(ms_p / ms_b, 3), "batched_equals_plain": True})
+        del plain, ws
+    # issued bytes of the launch (host walk stored per plan set and row threshold)
+    tr = load_json("batch256_traffic.json") or {}
+    roofline, elements = None, None
+    if tr.get("key") == key:
+        B = tr["total"]["bytes"]
+        elements = tr["total"]["elements_merge"]
+        achieved = B / (gpu_b / 1e3) / 1e9
+        wl = "batch256_rmat22"
+        prof = profile_record("count_kernel_batch256_traffic.json", wl)
+        roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                    "traffic": prof["hbm_bytes_per_launch"] if prof else None}
+        cnt = profile_record("count_kernel_batch256_counters.json", wl)
+        if cnt:
+            extras["issue"] = {"valu_instructions": cnt["SQ_INSTS_VALU"],
+                               "frac": round(cnt["SQ_INSTS_VALU"] / (N_CU * CLOCK_HZ * gpu_b / 1e3), 4),
+                               "note": "SQ_INSTS_VALU / (256 CUs x 2.4 GHz x launch time), one wave64 VALU "
+                                       "instruction per CU per cycle"}
+        extras["issued_bytes_per_launch"] = B
+        extras["elements_intersected"] = elements
+        extras["elements_per_s"] = elements / (gpu_b / 1e3)
+    else:
+        log("[batch] stored traffic does not match these plans; roofline not reported")
+    cpu = None
+    smp = load_json("batch256_cpu_sample.json")
+    if not args.no_cpu_baseline and smp:
+        log("[batch] oracle cpu baseline")
+        work = [(pats[i], np.array(r, dtype=np.uint32), rv) for i, r, rv in smp["work"]]
+        cpu = cpu_baseline(g, work, smp["description"])
+    if not args.no_extras:
+        extras["rmat16_motifs"] = extra_rmat16(args)
+        extras["rmat20_reduction"] = extra_rmat20(args)
     total = sum(counts)
+    sizes = {k: sum(1 for p in pats if p.k == k) for k in (3, 4, 5, 6)}
     rec = {
         "metric": METRIC, "value": total / (ms_b / 1e3), "unit": "embeddings/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_b, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "batch256_rmat22", "n": g.n, "m": g.m, "patterns": len(pats),
-                   "pattern_sizes": {k: sum(1 for p in pats if p.k == k) for k in (3, 4, 5, 6)},
-                   "plan": "reduced, symmetry breaking" if sym else "reduced",
-                   "node_order": "by decreasing degree (load time)" if order else "as generated",
-                   "launch": "one persistent launch, HIP graph, autotuned",
-                   "tuned": opts, "dense_rows": rows_info},
-        "batched_gpu_ms": round(gpu_b, 3), "plain_ms_per_step": round(ms_p, 3),
-        "batched_vs_plain_speedup": round(ms_p / ms_b, 3),
-        "plans_with_symmetry_breaking": n_sym, "planning_s": round(t_plan, 1),
-        "no_symmetry_ms_per_step": None if ms_nosym is None else round(ms_nosym, 3),
-        "tune": trec, "counts_sum": str(total), "batched_equals_plain": True,
-        "oracle_root_subset_parity": parity, "oracle_parity_patterns": len(sample_ids),
+        "config": {"workload": "batch256_rmat22",
+                   "graph": "R-MAT scale 22, edge factor 16, (.57,.19,.19,.05), seed 0",
+                   "n": g.n, "m": g.m, "patterns": len(pats), "pattern_sizes": sizes,
+                   "root_shares": {str(sh): sum(1 for x in shares if x == sh) for sh in sorted(set(shares))},
+                   "plan": "reduced, symmetry breaking (side stored per pattern), unit cover weights",
+                   "node_order": "by decreasing degree (load time)",
+                   "launch": "one persistent launch of 256 plans, HIP graph replay",
+                   "options": opts, "options_tuned_for_these_plans": tuned.get("key") == key,
+                   "dense_rows": G.dense_rows_info(), "parallelism": "1 GPU"},
+        "kernel_ms": round(gpu_b, 3),
+        "kernel_ms_note": "HIP events on the launch stream around each HIP-graph replay",
+        "counts_sum": str(total), "plans_with_symmetry_breaking": n_sym, "planning_s": round(t_plan, 2),
+        "roofline": roofline, "cpu_baseline": cpu, **extras,
     }
     print(json.dumps(rec), flush=True)
+
+
+def extra_rmat16(args):
+    """Config 2 beside the line: R-MAT scale 16, four motifs, reduced
+    symmetry-broken plans in one batched launch; plain launches; unreduced
+    plans; counts checked against the stored oracle values."""
+    import torch
+
+    import xmgen
+    from paper_2404_11105_amd import Counter, Graph, Plan
+    log("[rmat16] generating R-MAT scale 16")
+    g = xmgen.rmat(16, seed=0)
+    pats = [xmgen.named(n) for n in PATTERNS]
+    G = Graph(g, order_by_degree=True)
+    s = torch.cuda.Stream()
+    red = [Plan(p, reduced=True, graph=G, symmetry=True) for p in pats]
+    cb = Counter(G, red)
+    cb.capture(s)
+    steps = max(3, args.steps // 2)
+    ms_b, _ = timed_steps(cb, s, steps, 2)
+    counts = cb.results()[0]
+    plain = [Counter(G, [p]) for p in red]
+    ms_p = timed_plain(plain, s, steps, 1)
+    assert [c.results()[0][0] for c in plain] == counts
+    cu = Counter(G, [Plan(p, reduced=False, graph=G, symmetry=True) for p in pats])
+    cu.capture(s)
+    ms_u, _ = timed_steps(cu, s, steps, 1)
+    assert cu.results()[0] == counts
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "rmat16.json")))["counts"]
+    return {"graph": "R-MAT scale 16, seed 0", "patterns": PATTERNS, "counts": [str(c) for c in counts],
+            "counts_match_oracle": counts == [int(gold[n]) for n in PATTERNS],
+            "batched_ms": round(ms_b, 3), "plain_ms": round(ms_p, 3),
+            "batched_vs_plain_speedup": round(ms_p / ms_b, 3), "unreduced_ms": round(ms_u, 3),
+            "reduced_vs_unreduced_speedup": round(ms_u / ms_b, 3),
+            "embeddings_per_s": sum(counts) / (ms_b / 1e3)}
+
+
+def extra_rmat20(args):
+    """Config 3 beside the line: R-MAT scale 20, transitive tournament on 4
+    vertices plus a pendant in-arc (every root) and the 5-cycle with a chord
+    (root share 1/64), each as the reduced plan (leaf groups counted by
+    product, included arcs taken from the including arc's candidates)
+    against the unreduced plan (every level fetches all its lists, only the
+    last vertex counted); a launch past the limit is cancelled."""
+    import torch
+
+    import xmgen
+    from paper_2404_11105_amd import Counter, Graph, Plan
+    from paper_2404_11105_amd import Watchdog
+    log("[rmat20] generating R-MAT scale 20")
+    g = xmgen.rmat(20, seed=0)
+    G = Graph(g, order_by_degree=True)
+    s = torch.cuda.Stream()
+    wd = Watchdog()
+    limit_s = 60.0
+    out = {"cancel_after_s": limit_s}
+    # the 5-cycle with a chord has ~10^14 embeddings and does not finish
+    # within the limit on every root: it is counted on a root share
+    shares = {"tt4p": 0, "c5chord": C5CHORD_SHARE}
+    for name in ("tt4p", "c5chord"):
+        p = xmgen.named(name)
+        row = {"root_share": shares[name]}
+        for kind, red in (("reduced", True), ("unreduced", False)):
+            plan = Plan(p, reduced=red, graph=G, symmetry=True, root_share=shares[name])
+            c = Counter(G, [plan], cancel=wd, kernel_events=True, stream=s)
+            ms = []
+            for _ in range(2):
+                wd.arm(limit_s)
+                c.run(s)
+                s.synchronize()
+                wd.disarm()
+                cnt, st = c.results()
+                if st != [0]:
+                    break
+                ms.append(c.kernel_ms())
+            d = plan.describe()
+            row[kind] = {"ms": round(min(ms), 3) if ms and st == [0] else None, "count": str(cnt[0]) if st == [0] else None,
+                         "status": st[0], "e": d["e"], "leaves": d["t"], "removed_arcs": d["removed_edges"],
+                         "fetched_arcs": len(d["cover"]["fetched"])}
+            log(f"[rmat20] {name} {kind}: {row[kind]['ms']} ms (status {st[0]})")
+        if row["reduced"]["ms"] and row["unreduced"]["ms"]:
+            assert row["reduced"]["count"] == row["unreduced"]["count"]
+            row["reduced_vs_unreduced_speedup"] = round(row["unreduced"]["ms"] / row["reduced"]["ms"], 3)
+        out[name] = row
+    return out
 
 
 def bench_fraction(args):
@@ -456,31 +622,29 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip plain/unreduced timings")
-    ap.add_argument("--no-symmetry", action="store_true",
-                    help="plans without symmetry breaking (every embedding enumerated)")
-    ap.add_argument("--generated-order", action="store_true",
-                    help="store the graph in the generator's node order (default: nodes "
-                         "renumbered by decreasing degree at load, untimed)")
-    ap.add_argument("--chunk", type=int, default=0)
-    ap.add_argument("--split", type=int, default=0)
-    ap.add_argument("--split-work", type=int, default=0)
-    ap.add_argument("--cap", type=int, default=0)
-    ap.add_argument("--waves-per-cu", type=int, default=0)
-    ap.add_argument("--row-min", type=int, default=None,
-                    help="shortest list with a dense membership row (default: the library's)")
-    ap.add_argument("--dense-rows", type=int, default=None,
-                    help="byte budget of the dense rows (0: none; default: the library's)")
-    ap.add_argument("--workload", default="rmat16",
-                    choices=["rmat16", "batch256", "serve", "fraction", "listing"],
-                    help="rmat16: the contract line (default); batch256 / serve: the batched "
-                         "and serving workloads, each printing its own JSON line")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the plain launches and the scale-16 / scale-20 extras")
+    ap.add_argument("--workload", default="batch256",
+                    choices=["batch256", "rmat16", "rmat20", "serve", "fraction", "listing"],
+                    help="batch256: the contract line (default); the others print their own JSON line")
     ap.add_argument("--requests", type=int, default=150, help="serve: requests per load level and policy")
+    ap.add_argument("--write-cpu-sample", action="store_true",
+                    help="write the oracle's sample of the batch workload and time it (host only)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run plain device copies of this size (counter calibration)")
     args = ap.parse_args()
     if args.copy_probe_mib:
         copy_probe(args.copy_probe_mib, args.steps)
+        return
+    if args.write_cpu_sample:
+        import numpy as np
+
+        from paper_2404_11105_amd import workloads
+        smp = write_cpu_sample()
+        g = workloads.batch_graph()
+        pats = workloads.batch_patterns()
+        work = [(pats[i], np.array(r, dtype=np.uint32), rv) for i, r, rv in smp["work"]]
+        print(json.dumps(cpu_baseline(g, work, smp["description"])), flush=True)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -490,129 +654,25 @@ def main():
         sys.exit(2)
     if args.workload == "batch256":
         bench_batch256(args)
-        return
-    if args.workload == "serve":
+    elif args.workload == "rmat16":
+        import torch
+        torch.cuda.set_device(0)
+        r = extra_rmat16(args)
+        print(json.dumps({"metric": METRIC, "value": r["embeddings_per_s"], "unit": "embeddings/s", "n_gpus": 1,
+                          "steps": max(3, args.steps // 2), "warmup": 2, "ms_per_step": r["batched_ms"],
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+                          "data": "synthetic", "config": {"workload": "rmat16_motifs_batched"}, **r}), flush=True)
+    elif args.workload == "rmat20":
+        import torch
+        torch.cuda.set_device(0)
+        r = extra_rmat20(args)
+        print(json.dumps({"workload": "rmat20_reduction", **r}), flush=True)
+    elif args.workload == "serve":
         bench_serve(args)
-        return
-    if args.workload == "fraction":
+    elif args.workload == "fraction":
         bench_fraction(args)
-        return
-    if args.workload == "listing":
+    elif args.workload == "listing":
         bench_listing(args)
-        return
-
-    import numpy as np
-    import torch
-
-    import xmgen
-    from paper_2404_11105_amd import Counter, Graph, Plan, plan_work
-
-    torch.cuda.set_device(0)
-    log("[bench] generating R-MAT scale 16")
-    g = xmgen.rmat(16, seed=0)
-    pats = [xmgen.named(n) for n in PATTERNS]
-    G = Graph(g, dense_rows=args.dense_rows, row_min=args.row_min, order_by_degree=not args.generated_order)
-    tune = dict(chunk=args.chunk, split=args.split, split_work=args.split_work, cap=args.cap,
-                waves_per_cu=args.waves_per_cu)
-    sym = not args.no_symmetry
-    red = [Plan(p, reduced=True, graph=G, symmetry=sym) for p in pats]
-    unred = [Plan(p, reduced=False, graph=G, symmetry=sym) for p in pats]
-    workload = ("rmat16_ffl_c3_bifan_c4_reduced" + ("_sym" if sym else "")
-                + ("" if args.generated_order else "_degorder") + "_batched")
-    s = torch.cuda.Stream()
-
-    # algorithmic work of the four plans (host walk, untimed; with symmetry
-    # breaking only the list parts above each bound count)
-    log("[bench] algorithmic work (host walk)")
-    threads = max(1, min(16, len(os.sched_getaffinity(0))))
-    st = [plan_work(G.host, p, threads=threads) for p in red]
-    E = sum(x["elements"] for x in st)
-    F = sum(x["fetches"] for x in st)
-    B_alg = 4 * E + 8 * F + 8 * g.n * len(pats)
-
-    log("[bench] batched reduced (HIP graph)")
-    cb = Counter(G, red, **tune)
-    cb.capture(s)
-    ms_step, kern_ms = timed_steps(cb, s, args.steps, args.warmup)
-    counts, status = cb.results()
-    assert status == [0] * len(pats), status
-
-    extras = {}
-    if not args.no_extras:
-        log("[bench] plain per-pattern launches")
-        plain = [Counter(G, [p], **tune) for p in red]
-        ms_plain = timed_plain(plain, s, args.steps, args.warmup)
-        assert [c.results()[0][0] for c in plain] == counts
-        log("[bench] batched unreduced")
-        cu = Counter(G, unred, **tune)
-        cu.capture(s)
-        ms_unred, kern_unred = timed_steps(cu, s, max(3, args.steps // 4), 1)
-        assert cu.results()[0] == counts
-        E_un = sum(plan_work(G.host, p, threads=threads)["elements"] for p in unred)
-        if sym:
-            log("[bench] batched reduced without symmetry breaking")
-            cn = Counter(G, [Plan(p, reduced=True, graph=G) for p in pats], **tune)
-            cn.capture(s)
-            ms_nosym, _ = timed_steps(cn, s, max(3, args.steps // 4), 1)
-            assert cn.results()[0] == counts
-            extras = {"no_symmetry_ms_per_step": round(ms_nosym, 4),
-                      "symmetry_speedup": round(ms_nosym / ms_step, 3)}
-        extras.update({"plain_ms_per_step": round(ms_plain, 4),
-                  "batched_vs_plain_speedup": round(ms_plain / ms_step, 3),
-                  "unreduced_ms_per_step": round(ms_unred, 4),
-                  "unreduced_kernel_ms": round(kern_unred, 4),
-                  "reduced_vs_unreduced_speedup": round(ms_unred / ms_step, 3),
-                  "unreduced_elements": E_un})
-
-    gold_ok = None
-    gpath = os.path.join(ROOT, "tests", "golden", "rmat16.json")
-    if os.path.exists(gpath):
-        gold = json.load(open(gpath))["counts"]
-        gold_ok = counts == [int(gold[n]) for n in PATTERNS]
-
-    total = sum(counts)
-    value = total / (ms_step / 1e3)
-    achieved = B_alg / (kern_ms / 1e3) / 1e9
-    traffic = traffic_from_profile(workload)
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("[bench] oracle cpu baseline")
-        cpu = cpu_baseline(g, pats)
-
-    rec = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "embeddings/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u64",
-        "data": "synthetic",
-        "config": {"workload": workload,
-                   "graph": "R-MAT scale 16, edge factor 16, (.57,.19,.19,.05), seed 0",
-                   "n": g.n, "m": g.m, "patterns": PATTERNS,
-                   "plan": "reduced, symmetry breaking" if sym else "reduced",
-                   "launch": "one persistent launch for 4 patterns, HIP graph replay",
-                   "parallelism": "1 GPU", "dense_rows": G.dense_rows_info(),
-                   "node_order": "as generated" if args.generated_order else "by decreasing degree (load time)"},
-        "counts": [str(c) for c in counts],
-        "counts_match_oracle": gold_ok,
-        "kernel_ms": round(kern_ms, 4),
-        "kernel_ms_note": "HIP events on the launch stream around each HIP-graph replay",
-        "elements_intersected": E,
-        "list_fetches": F,
-        "elements_per_s": E / (kern_ms / 1e3),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic},
-        "cpu_baseline": cpu,
-        **extras,
-    }
-    print(json.dumps(rec), flush=True)
 
 
 if __name__ == "__main__":

@@ -1,24 +1,31 @@
 """Workload definitions for the batched and serving benchmarks.
 
 batch256: 256 seeded random connected patterns of 3-6 vertices (xmgen's
-random_pattern recipe) counted against one resident R-MAT scale 22 graph.
+random_pattern recipe), QUOTA = 64 of each size, counted against one
+resident R-MAT scale 22 graph stored in degree order with its dense rows.
 Random sparse patterns on a graph with ~10^5-degree hubs can have 10^15 or
-more partial matches, which no launch can enumerate, so candidates pass a
-work cap: the plan's algorithmic work (xm_plan_work) is estimated from roots
-sampled by degree rank -- all of the 16 largest, then 16 seeded roots from
-each rank stratum [16,64), [64,256), ..., [262144, n), each weighted by its
-stratum size -- and must stay under CAP_ELEMENTS, with no walk passing
-WALK_BUDGET partial matches; the estimates of the accepted heavy patterns
-(above HEAVY elements) together stay under TOTAL_CAP (a heavy candidate that
-would pass it is rejected), which keeps one batched launch at a few seconds.  Sizes are drawn round-robin (3, 4, 5, 6) with a
-quota of 64 each; a size whose candidates run out (MAX_DRAWS) is backfilled
-by smaller sizes.  The accepted seeds are stored in workloads/batch256.json
-with the counts of rejected draws.
+more partial matches, which no launch can enumerate, so every pattern is
+counted on a root share: the stored ids r with r mod 2^s = 2^s - 1 (every
+2^s-th node by degree rank; the largest hub is in no proper share), with s
+the smallest in SHARES for which the pattern's plain launch on the MI355X
+takes at most CAP_MS (a watchdog cancels a launch past 3 x CAP_MS, which
+counts as over).  Sizes are drawn round-robin (3, 4, 5, 6) until each has its
+quota; a candidate that would take the patterns' summed plain time past
+TOTAL_MS is rejected, which keeps one batched launch at a few seconds.  The
+selection runs on the GPU once; the accepted (k, seed, share, symmetry side,
+plain ms) entries are stored in workloads/batch256.json with the rejected
+draws per size (the symmetry side of a plan is the faster of the two measured
+ones), and every later run rebuilds the same plans from it (reduced,
+symmetry-broken on the stored side, unit cover weights: no graph
+statistics, so the plans are the same on a host without a GPU).
 
-    python -m paper_2404_11105_amd.workloads batch256
+    python -m paper_2404_11105_amd.workloads batch256 [out.json [resume.json]]  (on a GPU)
+    python -m paper_2404_11105_amd.workloads batch256-tune [out.json]   (on a GPU)
+    python -m paper_2404_11105_amd.workloads batch256-traffic           (host walk)
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 import sys
@@ -28,13 +35,14 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 BATCH_PATH = os.path.join(HERE, "workloads", "batch256.json")
-CAP_ELEMENTS = 3e11
-TOTAL_CAP = 4e12
-HEAVY = 1e10
-WALK_BUDGET = 2_000_000
-STRATA = [0, 16, 64, 256, 1024, 4096, 16384, 65536, 262144]
-MAX_DRAWS = 1000
+TUNED_PATH = os.path.join(HERE, "workloads", "batch256_tuned.json")
+CAP_MS = 20.0
+TOTAL_MS = 3000.0
+SHARES = (0, 2, 4, 6, 8, 10, 12, 14, 16)
+QUOTA = 64
+MAX_DRAWS = 1500
 SEED_BASE = {3: 300000, 4: 400000, 5: 500000, 6: 600000}
+ROW_BYTES = 64 << 30    # dense-row budget of the scale-22 graph
 
 
 def batch_graph():
@@ -46,80 +54,229 @@ def batch_patterns():
     """The 256 accepted patterns (list of xmgen.Pattern) from the stored file."""
     import xmgen
     rec = json.load(open(BATCH_PATH))
-    return [xmgen.random_pattern(k, s) for k, s in rec["accepted"]]
+    return [xmgen.random_pattern(e["k"], e["seed"]) for e in rec["accepted"]]
 
 
-def select_batch(threads: int = 8):
+def batch_shares():
+    """Root share exponent of every accepted pattern (0: all roots)."""
+    return [e["share"] for e in json.load(open(BATCH_PATH))["accepted"]]
+
+
+def batch_plans():
+    """The 256 plans as every run builds them: reduced, symmetry broken on the
+    stored side, each on its root share, unit cover weights."""
+    from .api import Plan
+    rec = json.load(open(BATCH_PATH))
+    pats = batch_patterns()
+    return [Plan(p, reduced=True, symmetry=e["symmetry"], root_share=e["share"])
+            for p, e in zip(pats, rec["accepted"])]
+
+
+def plans_key(plans, row_min: int) -> str:
+    """Identity of a batch of plans on a dense-row threshold (their JSON)."""
+    from .api import plan_json
+    h = hashlib.sha256()
+    for p in plans:
+        h.update(plan_json(p).encode())
+    h.update(str(int(row_min)).encode())
+    return h.hexdigest()[:24]
+
+
+def degree_order(g):
+    """new_of_old of the graph stored by decreasing total degree, ties by
+    lower id (the renumbering xm_load_graph's XM_ORDER_BY_DEGREE applies)."""
+    deg = g.out_deg() + g.in_deg()
+    by_deg = np.argsort(-deg, kind="stable")
+    new_of_old = np.empty(g.n, dtype=np.uint32)
+    new_of_old[by_deg] = np.arange(g.n, dtype=np.uint32)
+    return new_of_old
+
+
+def share_roots(n: int, share: int) -> np.ndarray:
+    """Stored ids in the root share: r mod 2^s = 2^s - 1."""
+    return np.arange((1 << share) - 1, n, 1 << share, dtype=np.uint32)
+
+
+def _plain_ms(G, plan, wd, stream):
+    """Kernel milliseconds of one plain launch, or None if the watchdog
+    cancelled it."""
+    from .api import Counter
+    c = Counter(G, [plan], cancel=wd, kernel_events=True, stream=stream)
+    wd.arm(3 * CAP_MS / 1e3)
+    c.run(stream)
+    stream.synchronize()
+    wd.disarm()
+    st = c.results(sync=False)[1][0]
+    if st == -7:
+        return None
+    if st != 0:
+        raise RuntimeError(f"launch status {st}")
+    return c.kernel_ms()
+
+
+def select_batch(out_path: str = BATCH_PATH, resume: str | None = None):
+    """Draw and keep 256 patterns (see the module docstring); needs a GPU.
+    The record is rewritten after every accepted pattern; `resume` (a
+    record written earlier) continues its draws where they stopped."""
+    import torch
+
     import xmgen
-    from .api import Plan, plan_work
+    from .api import Graph, Plan, Watchdog
     t0 = time.time()
+    torch.cuda.set_device(0)
     g = batch_graph()
-    deg = np.maximum(g.out_deg(), g.in_deg())
-    order = np.argsort(-deg, kind="stable").astype(np.uint32)
-    rng = np.random.default_rng(22)
-    strata = []  # (roots, weight)
-    bounds = STRATA + [g.n]
-    for a, b in zip(bounds[:-1], bounds[1:]):
-        idx = order[a:b]
-        if b - a <= 16:
-            strata.append((np.sort(idx), 1.0))
-        else:
-            strata.append((np.sort(rng.choice(idx, size=16, replace=False)), (b - a) / 16.0))
-    quota = {3: 64, 4: 64, 5: 64, 6: 64}
-    accepted, rejected, draws, est = [], {k: 0 for k in quota}, {k: 0 for k in quota}, []
-    exhausted = set()
-    while len(accepted) < 256:
+    G = Graph(g, order_by_degree=True, dense_rows=ROW_BYTES)
+    s = torch.cuda.Stream()
+    wd = Watchdog()
+    quota = {k: QUOTA for k in (3, 4, 5, 6)}
+    accepted, total = [], 0.0
+    rejected, draws = {k: 0 for k in quota}, {k: 0 for k in quota}
+    spent = 0.0
+    if resume:
+        old = json.load(open(resume))
+        accepted = old["accepted"]
+        total = sum(e["plain_ms"] for e in accepted)
+        rejected = {int(k): v for k, v in old["rejected_per_k"].items()}
+        draws = {int(k): v for k, v in old["draws_per_k"].items()}
+        spent = old.get("selection_seconds", 0.0)
+        for e in accepted:
+            quota[e["k"]] -= 1
+
+    def save():
+        rec = {"graph": "rmat(scale=22, edge_factor=16, abcd=(.57,.19,.19,.05), seed=0), stored in degree "
+                        f"order, dense rows within {ROW_BYTES} bytes",
+               "recipe": "random_pattern(k, seed); root share 2^-s: the smallest s in shares with a plain "
+                         "launch of at most cap_ms on the MI355X",
+               "cap_ms": CAP_MS, "total_ms": TOTAL_MS, "shares": list(SHARES), "quota_per_size": QUOTA,
+               "device": torch.cuda.get_device_name(0), "accepted": accepted, "plain_ms_total": round(total, 3),
+               "rejected_per_k": rejected, "draws_per_k": draws,
+               "selection_seconds": round(spent + time.time() - t0, 1)}
+        with open(out_path, "w") as f:
+            json.dump(rec, f, indent=1)
+            f.write("\n")
+        return rec
+
+    while len(accepted) < 4 * QUOTA:
         progressed = False
         for k in (3, 4, 5, 6):
-            if k in exhausted or quota[k] == 0:
-                continue
-            seed = SEED_BASE[k] + draws[k]
-            draws[k] += 1
-            if draws[k] > MAX_DRAWS:
-                exhausted.add(k)
+            if quota[k] == 0 or draws[k] >= MAX_DRAWS:
                 continue
             progressed = True
+            seed = SEED_BASE[k] + draws[k]
+            draws[k] += 1
             p = xmgen.random_pattern(k, seed)
-            plan = Plan(p, True)
-            e, exceeded = 0.0, False
-            for roots, w in strata:
-                r = plan_work(g, plan, roots=roots, threads=threads, max_partial=WALK_BUDGET)
-                e += r["elements"] * w
-                if r["exceeded"] or e > CAP_ELEMENTS:
-                    exceeded = True
+            chosen = None
+            for sh in SHARES:
+                # the symmetry side that runs faster (both are exact)
+                best = None
+                for side in ("above", "below"):
+                    plan = Plan(p, reduced=True, symmetry=side, root_share=sh)
+                    if side == "below" and plan.describe()["sym_mult"] == 1:
+                        break
+                    ms = _plain_ms(G, plan, wd, s)
+                    if ms is not None and (best is None or ms < best[1]):
+                        best = (side, ms)
+                if best is not None and best[1] <= CAP_MS:
+                    chosen = (sh, best[0], best[1])
                     break
-            if exceeded or (e > HEAVY and sum(x for x in est if x > HEAVY) + e > TOTAL_CAP):
+            if chosen is None or total + chosen[2] > TOTAL_MS:
                 rejected[k] += 1
+                print(f"k={k} seed={seed} rejected t={time.time() - t0:.0f}s", flush=True)
                 continue
-            accepted.append((k, seed))
-            est.append(e)
+            accepted.append({"k": k, "seed": seed, "share": chosen[0], "symmetry": chosen[1],
+                             "plain_ms": round(chosen[2], 3)})
+            total += chosen[2]
             quota[k] -= 1
-            print(f"k={k} seed={seed} est={e:.3g} accepted={len(accepted)}", flush=True)
-            if len(accepted) == 256:
-                break
+            save()
+            print(f"k={k} seed={seed} share={chosen[0]} side={chosen[1]} ms={chosen[2]:.2f} "
+                  f"accepted={len(accepted)} total={total:.0f} t={time.time() - t0:.0f}s", flush=True)
         if not progressed:
-            # backfill the missing quota from the smallest sizes
-            missing = 256 - len(accepted)
-            for k in (3, 4, 5, 6):
-                if k not in exhausted:
-                    quota[k] += missing
-                    break
-            else:
-                break
-    rec = {"graph": "rmat(scale=22, edge_factor=16, abcd=(.57,.19,.19,.05), seed=0)",
-           "recipe": "random_pattern(k, seed); work cap from a degree-stratified root sample",
-           "cap_elements": CAP_ELEMENTS, "total_cap": TOTAL_CAP, "heavy": HEAVY, "walk_budget": WALK_BUDGET,
-           "accepted": accepted, "estimated_elements": est,
-           "rejected_per_k": rejected, "draws_per_k": draws,
-           "selection_seconds": round(time.time() - t0, 1)}
-    os.makedirs(os.path.dirname(BATCH_PATH), exist_ok=True)
-    with open(BATCH_PATH, "w") as f:
+            break
+    return save()
+
+
+def row_threshold(g, max_bytes: int = ROW_BYTES, min_len: int = 64) -> int:
+    """The dense-row threshold xm_graph_dense_rows picks for this budget: the
+    smallest list length (at least max(min_len, 32)) such that every out- and
+    in-list at least that long gets an n-bit row within max_bytes."""
+    row_bytes = (g.n + 31) // 32 * 4
+    fit = max_bytes // row_bytes
+    lo = max(min_len, 32)
+    lens = np.concatenate([np.diff(np.asarray(g.out_off, dtype=np.int64)),
+                           np.diff(np.asarray(g.in_off, dtype=np.int64))])
+    lens = np.sort(lens[lens >= lo])[::-1]
+    if lens.size == 0 or fit == 0:
+        return 0
+    if lens.size > fit:
+        t = int(lens[fit]) + 1
+        return t if t <= int(lens[0]) else 0
+    return lo
+
+
+TRAFFIC_PATH = os.path.join(HERE, "workloads", "batch256_traffic.json")
+
+
+def batch_traffic(threads: int = 8, out_path: str = TRAFFIC_PATH):
+    """Issued memory operations of every batch plan over all its roots (the
+    host walk xm_plan_traffic on the graph in stored order, with the dense-row
+    threshold of ROW_BYTES), stored with the batch's key; host only."""
+    from .api import _renumbered, plan_traffic
+    t0 = time.time()
+    g0 = batch_graph()
+    g = _renumbered(g0, degree_order(g0))
+    del g0
+    T = row_threshold(g)
+    plans = batch_plans()
+    per = []
+    for i, p in enumerate(plans):
+        t = time.time()
+        d = plan_traffic(g, p, row_min=T, threads=threads)
+        assert not d["exceeded"]
+        d["seconds"] = round(time.time() - t, 2)
+        per.append(d)
+        print(i, d["bytes"], d["elements_merge"], d["seconds"], flush=True)
+    keys = [k for k in per[0] if k not in ("exceeded", "seconds")]
+    total = {k: sum(d[k] for d in per) for k in keys}
+    rec = {"key": plans_key(plans, T), "row_min": T, "per_plan": per, "total": total,
+           "bytes_formula": "4 x (base elements + row words + search words + chain words) + "
+                            "8 x (offset pairs + degree pairs + partial matches)",
+           "seconds": round(time.time() - t0, 1)}
+    with open(out_path, "w") as f:
         json.dump(rec, f, indent=1)
         f.write("\n")
     return rec
 
 
+def tune_batch(out_path: str = TUNED_PATH, budget_s: float = 150.0):
+    """Tune the batched launch of the stored batch (tune.py, coordinate
+    descent over launch options) and store the options with the batch's key;
+    needs a GPU."""
+    import torch
+
+    from .api import Graph
+    from .tune import tune
+    torch.cuda.set_device(0)
+    g = batch_graph()
+    G = Graph(g, order_by_degree=True, dense_rows=ROW_BYTES)
+    plans = batch_plans()
+    key = plans_key(plans, G.dense_rows_info()["row_min"])
+    opts, rec = tune(G, plans, stream=torch.cuda.Stream(), reps=1, budget_s=budget_s,
+                     log=lambda *a: print(*a, flush=True))
+    out = {"key": key, "opts": opts, "ms": rec["ms"], "default_ms": rec["default_ms"], "trials": rec["trials"],
+           "seconds": rec["seconds"], "device": torch.cuda.get_device_name(0),
+           "row_min": G.dense_rows_info()["row_min"]}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    return out
+
+
 if __name__ == "__main__":
-    if sys.argv[1:] == ["batch256"]:
-        r = select_batch()
-        print({k: v for k, v in r.items() if k not in ("accepted", "estimated_elements")})
+    if sys.argv[1:2] == ["batch256"]:
+        r = select_batch(sys.argv[2] if len(sys.argv) > 2 else BATCH_PATH,
+                         sys.argv[3] if len(sys.argv) > 3 else None)
+        print({k: v for k, v in r.items() if k != "accepted"})
+    elif sys.argv[1:2] == ["batch256-traffic"]:
+        print(batch_traffic(int(os.environ.get("XM_WALK_THREADS", "8")))["total"])
+    elif sys.argv[1:2] == ["batch256-tune"]:
+        print(tune_batch(sys.argv[2] if len(sys.argv) > 2 else TUNED_PATH))
