@@ -42,6 +42,13 @@ def _load():
         lib.xmo_list.argtypes = [ctypes.c_uint32, P, P, ctypes.c_int, ctypes.c_int, P,
                                  P, ctypes.c_uint64, ctypes.c_int, P, ctypes.c_uint64, P, P]
         lib.xmo_list.restype = ctypes.c_int
+        lib.xmo_prepare.argtypes = [ctypes.c_uint32, P, P]
+        lib.xmo_prepare.restype = ctypes.c_void_p
+        lib.xmo_count_prepared.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, ctypes.c_uint64, ctypes.c_int,
+                                           ctypes.c_int, P, P, P, ctypes.c_int, P]
+        lib.xmo_count_prepared.restype = ctypes.c_int
+        lib.xmo_release.argtypes = [P]
+        lib.xmo_release.restype = None
         _lib = lib
     return _lib
 
@@ -113,3 +120,45 @@ def list_embeddings(graph, pattern, cap: int, roots=None, root_vertex: int = -1)
         raise ValueError(f"oracle rejected the input (code {rc})")
     total = lo.value | (hi.value << 64)
     return total, out[:min(total, cap)]
+
+
+class Prepared:
+    """A graph whose in-lists the oracle built once (graph pre-processing):
+    count() gives exactly oracle.count()'s values without rebuilding them.
+    The graph's arrays must stay alive while this object is used."""
+
+    def __init__(self, graph):
+        lib = _load()
+        self.n = graph.n
+        self._off = np.ascontiguousarray(graph.out_off, dtype=np.uint32)
+        self._adj = np.ascontiguousarray(graph.out_adj, dtype=np.uint32)
+        if self._adj.size == 0:
+            self._adj = np.zeros(1, dtype=np.uint32)
+        self._h = lib.xmo_prepare(graph.n, _ptr(self._off), _ptr(self._adj))
+        if not self._h:
+            raise MemoryError("oracle could not prepare the graph")
+
+    def count(self, pattern, roots=None, mode: str = "A", threads: int = 1, root_vertex: int = -1) -> int:
+        arcs = np.frombuffer(pattern.arcs_u8(), dtype=np.uint8).copy()
+        if arcs.size == 0:
+            arcs = np.zeros(2, dtype=np.uint8)
+        r = None if roots is None else np.ascontiguousarray(roots, dtype=np.uint32)
+        nr = 0 if r is None else int(r.size)
+        lo, hi = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        rc = _load().xmo_count_prepared(ctypes.c_void_p(self._h), pattern.k, len(pattern.arcs), _ptr(arcs),
+                                        _ptr(r), nr, {"A": 0, "B": 1}[mode], threads, ctypes.byref(lo),
+                                        ctypes.byref(hi), None, int(root_vertex), None)
+        if rc != 0:
+            raise ValueError(f"oracle rejected the input (code {rc})")
+        return lo.value | (hi.value << 64)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _load().xmo_release(ctypes.c_void_p(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

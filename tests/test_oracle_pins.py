@@ -168,3 +168,18 @@ def test_oracle_listing_equals_brute_force_maps(name):
         total2, part = oracle.list_embeddings(g, pat, cap=3)
         assert total2 == total and len(part) == min(3, total)
         assert all(any((r == w).all() for w in want) for r in part.astype(np.int64))
+
+
+def test_prepared_graph_gives_the_same_counts():
+    """Counting on a graph whose in-lists were built once (graph
+    pre-processing kept out of timings) gives the plain call's counts."""
+    g = xmgen.rmat(7, seed=3)
+    pr = oracle.Prepared(g)
+    roots = np.arange(1, g.n, 7, dtype=np.uint32)
+    for name in ["ffl", "bifan", "tt4p", "c5chord", "mixed_star"]:
+        p = xmgen.named(name)
+        for mode in ("A", "B"):
+            assert pr.count(p, mode=mode) == oracle.count(g, p, mode=mode)
+            assert pr.count(p, roots=roots, mode=mode, root_vertex=1, threads=3) == \
+                oracle.count(g, p, roots=roots, mode=mode, root_vertex=1)
+    pr.close()
