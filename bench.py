@@ -113,19 +113,18 @@ def host_cores() -> int:
         return os.cpu_count() or 1
 
 
-def oracle_timing(g, work, threads, reps=5):
-    """The oracle as it stands on `work` = [(pattern, roots, root_vertex)]:
-    one warm-up pass, then the median of `reps` timed passes (embeddings,
-    seconds).  With threads > 1 the work items run concurrently, one oracle
-    call per item on its own host thread (the oracle's own threads split a
-    call's roots 64 at a time, too coarse for these samples)."""
+def oracle_timing(prep, work, threads, reps=5):
+    """The oracle as it stands on `work` = [(pattern, roots, root_vertex)] over
+    a prepared graph (its in-lists built once, untimed, like the device
+    graph's load): one warm-up pass, then the median of `reps` timed passes
+    (embeddings, seconds).  With threads > 1 the work items run concurrently,
+    one oracle call per item on its own host thread (the oracle's own threads
+    split a call's roots 64 at a time, too coarse for these samples)."""
     from concurrent.futures import ThreadPoolExecutor
-
-    import oracle
 
     def item(w):
         p, r, rv = w
-        return oracle.count(g, p, roots=r, root_vertex=rv, mode="B")
+        return prep.count(p, roots=r, root_vertex=rv, mode="B")
 
     def one():
         t = time.perf_counter()
@@ -144,9 +143,12 @@ def oracle_timing(g, work, threads, reps=5):
 def cpu_baseline(g, work, sample_desc):
     """1 core and all T cores, each 1 warm-up + median of 5; `value` is the
     all-core rate (embeddings/s), the 1-core rate is beside it."""
+    import oracle
     T = host_cores()
-    c1, t1 = oracle_timing(g, work, 1)
-    cT, tT = oracle_timing(g, work, T)
+    prep = oracle.Prepared(g)
+    c1, t1 = oracle_timing(prep, work, 1)
+    cT, tT = oracle_timing(prep, work, T)
+    prep.close()
     assert c1 == cT
     return {"value": cT / tT, "unit": "embeddings/s", "cores": T, "kind": "oracle",
             "sample": sample_desc + f"; {cT} embeddings; median of 5 after 1 warm-up: {tT:.3f} s on {T} "
@@ -154,13 +156,15 @@ def cpu_baseline(g, work, sample_desc):
             "value_1core": c1 / t1, "seconds_1core": round(t1, 4), "seconds_all_cores": round(tT, 4)}
 
 
-def write_cpu_sample(n_patterns=16, per_pattern=64, chunks=4):
+def write_cpu_sample(n_patterns=16, per_pattern=128, chunks=8):
     """The oracle's sample of the batch workload (stored in
     workloads/batch256_cpu_sample.json; chosen from the stored batch without
-    running anything): every 16th pattern (four of each size) on 64 roots of
-    its own root share of degree rank [n/64, n/16) (lists of tens of arcs: the
-    bulk of the roots a launch walks; hubs are out of the oracle's reach in
-    seconds), in the generated ids, split into 4 work items per pattern."""
+    running anything): every 16th pattern (four of each size) on 128 roots of
+    its own root share of degree rank [n/16, n/4) (all of them when the share
+    has fewer there; lists of a few to ten arcs: the bulk of the roots a
+    launch walks; two roots of degree rank in [n/64, n/16) already took the
+    oracle over a minute for a six-vertex pattern), in the generated ids,
+    split into 8 work items per pattern."""
     import numpy as np
 
     from paper_2404_11105_amd import workloads
@@ -174,13 +178,13 @@ def write_cpu_sample(n_patterns=16, per_pattern=64, chunks=4):
     work = []
     for i in range(0, len(rec), len(rec) // n_patterns):
         sh = workloads.share_roots(g.n, rec[i]["share"])
-        sh = sh[(sh >= g.n // 64) & (sh < g.n // 16)]
-        roots = np.sort(old_of_new[rng.choice(sh, size=per_pattern, replace=False)])
+        sh = sh[(sh >= g.n // 16) & (sh < g.n // 4)]
+        roots = np.sort(old_of_new[rng.choice(sh, size=min(per_pattern, sh.size), replace=False)])
         rv = plans[i].describe()["root_vertex"]
         for c in np.array_split(roots, chunks):
             work.append([i, c.tolist(), rv])
-    desc = (f"{n_patterns} of the 256 patterns (every 16th), {per_pattern} roots each from its root share at "
-            f"degree ranks [n/64, n/16), generated ids, {chunks} work items per pattern")
+    desc = (f"{n_patterns} of the 256 patterns (every 16th), up to {per_pattern} roots each from its root share "
+            f"at degree ranks [n/16, n/4), generated ids, {chunks} work items per pattern")
     out = {"description": desc, "work": work}
     with open(os.path.join(WL_DIR, "batch256_cpu_sample.json"), "w") as f:
         json.dump(out, f)

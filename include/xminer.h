@@ -223,7 +223,7 @@ int xm_plan_work(uint32_t n, const uint32_t* out_off, const uint32_t* out_adj,
  * every window holds whole candidate sets (no hub sub-ranges or donated
  * prefixes).  out[XM_TRAFFIC_WORDS]:
  *   [0] base elements scanned (4 B each)     [1] offset pairs read (8 B)
- *   [2] degree pairs read (8 B)               [3] dense-row words tested (4 B)
+ *   [2] degree classes read (1 B)             [3] dense-row words tested (4 B)
  *   [4] sorted-list searches                  [5] words those searches load (4 B)
  *   [6] partial matches written (8 B: node, parent)
  *   [7] words of ancestor chains read back (4 B)

@@ -457,8 +457,8 @@ def plan_traffic(digraph, plan: Plan, row_min: int = 0, roots=None, threads: int
     """Memory operations the count kernel issues for `plan` on a host graph
     (xm_plan_traffic; statistics only, no count).  row_min: the graph's dense
     row threshold (0: no rows).  The dict also holds `bytes`: 4 B per base
-    element, row word, search word and chain word, 8 B per offset pair,
-    degree pair and partial match written."""
+    element, row word, search word and chain word, 8 B per offset pair and
+    partial match written, 1 B per degree class read."""
     arrs = [np.ascontiguousarray(a, dtype=np.uint32) for a in
             (digraph.out_off, digraph.out_adj, digraph.in_off, digraph.in_adj)]
     arrs = [a if a.size else np.zeros(1, dtype=np.uint32) for a in arrs]
@@ -480,7 +480,7 @@ def plan_traffic(digraph, plan: Plan, row_min: int = 0, roots=None, threads: int
 def traffic_bytes(d: dict) -> int:
     """Bytes of the issued model: what the kernel's tests read and write."""
     return (4 * (d["base_elements"] + d["row_words"] + d["search_words"] + d["chain_words"])
-            + 8 * (d["offset_pairs"] + d["degree_pairs"] + d["partial_matches"]))
+            + 8 * (d["offset_pairs"] + d["partial_matches"]) + d["degree_pairs"])
 
 
 class Watchdog:

@@ -239,7 +239,7 @@ def batch_traffic(threads: int = 8, out_path: str = TRAFFIC_PATH):
     total = {k: sum(d[k] for d in per) for k in keys}
     rec = {"key": plans_key(plans, T), "row_min": T, "per_plan": per, "total": total,
            "bytes_formula": "4 x (base elements + row words + search words + chain words) + "
-                            "8 x (offset pairs + degree pairs + partial matches)",
+                            "8 x (offset pairs + partial matches) + 1 x degree class reads",
            "seconds": round(time.time() - t0, 1)}
     with open(out_path, "w") as f:
         json.dump(rec, f, indent=1)

@@ -102,9 +102,11 @@ def _per_root(g, pat, roots, root_vertex, workers):
     per call and releases the interpreter while it counts)."""
     from concurrent.futures import ThreadPoolExecutor
 
+    prep = oracle.Prepared(g)  # in-lists built once for every root
+
     def one(r):
         t = time.time()
-        c = oracle.count(g, pat, roots=np.array([r], dtype=np.uint32), root_vertex=root_vertex, mode="B")
+        c = prep.count(pat, roots=np.array([r], dtype=np.uint32), root_vertex=root_vertex, mode="B")
         print(pat.name, int(r), c, round(time.time() - t, 1), flush=True)
         return str(c), round(time.time() - t, 1)
 
@@ -160,10 +162,17 @@ def batch_subsets(workers=None):
     old_of_new[new_of_old] = np.arange(g.n, dtype=np.uint32)
     pats = workloads.batch_patterns()
     out = []
+    path = os.path.join(HERE, "batch256_subsets.json")
+    if os.path.exists(path):  # continue a run that stopped: keep the patterns done
+        out = [r for r in json.load(open(path))["patterns"] if r["index"] in pick]
     for i in pick:
+        if any(r["index"] == i for r in out):
+            continue
         e = acc[i]
         share = workloads.share_roots(g.n, e["share"])
-        stored = np.concatenate([share[:2], np.sort(rng.choice(share[2:], size=30, replace=False))])
+        ri = np.random.default_rng(2560 + i)
+        stored = np.concatenate([share[:2], np.sort(ri.choice(share[2:], size=min(30, share.size - 2),
+                                                                replace=False))])
         roots = old_of_new[stored]
         from paper_2404_11105_amd.api import Plan
         rv = Plan(pats[i], reduced=True, symmetry=e["symmetry"], root_share=e["share"]).describe()["root_vertex"]
