@@ -230,6 +230,8 @@ struct Ctx {
     unsigned long long acc_lo, acc_hi;  // per-lane 128-bit partial (leaf groups)
     bool ovf;                           // this lane's partial or a leaf-group term left the 128-bit range
     bool donated;                       // this wave has handed off work (it then always waits)
+    bool stop;                          // the cancel flag was seen: leave the task
+    uint32_t polls;                     // leaf blocks since the last look at the cancel flag
 };
 
 // First-level base list length of root r for plan P (shortest constraint list).
@@ -777,6 +779,17 @@ __device__ void count_leaves(Ctx& C, uint32_t lv, uint32_t nprefix) {
     const uint32_t nb = lv + 1;  // bound levels 0..lv
     const LK S0 = load_lk(P->sig[0], a);
     for (uint32_t w0 = 0; w0 < nprefix; w0 += 64) {
+        // a leaf pass over hub lists can run long: look at the cancel flag
+        // every 8 blocks of 64 prefixes
+        if (a.cancel && (++C.polls & 7u) == 0) {
+            uint32_t stop = 0;
+            if (lane == 0) stop = __atomic_load_n(a.cancel, __ATOMIC_RELAXED) != 0;
+            if (uni(__shfl(stop, 0, 64))) {
+                if (lane == 0) atomicOr(&a.ctl[kCtlCancelled], 1u);
+                C.stop = true;
+                return;
+            }
+        }
         const uint32_t p = w0 + lane;
         const bool pv = p < nprefix;
         // walk the chain once: bound nodes of levels 0..lv
@@ -1007,6 +1020,7 @@ __device__ void explore(Ctx& C, uint32_t n0, uint32_t start) {
         uint32_t nout = expand(C, lv);
         if (lv == e - 1) {
             if (nout) count_leaves<NONLIN>(C, lv, nout);
+            if (C.stop) break;
         } else if (nout) {
             lv += 1;
             if (C.lane == 0) {
@@ -1037,6 +1051,8 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
     C.pi = 0;
     C.P = a.plans;
     C.donated = false;
+    C.stop = false;
+    C.polls = 0;
     // this wave's home split queue: the XCD its block runs on (blocks go to
     // the 8 XCDs round-robin), so a hub's sub-range tasks share one L2
     const uint32_t home = blockIdx.x % kQueues;
@@ -1216,7 +1232,10 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
         }
         wave_sync();
         if (n0) explore<NONLIN>(C, n0, start);
+        if (C.stop) break;
     }
+    // a wave that was counted as active must not stay so after a cancel
+    if (C.lane == 0 && C.stop && active) atomicSub(&a.ctl[kCtlActive], 1u);
     flush(C);
 }
 
