@@ -20,7 +20,10 @@ at v and its launch is restricted to the root subset {x}; anchored requests
 batch with others on the same graph and node.  A request may also carry a
 root subset, roots = (v, nodes): the embeddings that map v into `nodes` (an
 exact partial count); it batches with requests on the same graph and the
-same node array.
+same node array.  A request may instead carry a root share s: only the
+embeddings whose start vertex maps to a stored id r with r mod 2^s = 2^s - 1
+(the plan's XM_PLAN_ROOT_SHARE); the share is part of the plan, so such
+requests batch with any other on the same graph.
 
 Order: policy "fifo" takes the oldest pending request first; policy "sjf"
 takes the request with the smallest estimated cost first (the backend's
@@ -54,6 +57,7 @@ class Request:
     future: Future
     pin: tuple | None = None      # (pattern vertex, data node)
     roots: tuple | None = None    # (pattern vertex, uint32 node array)
+    share: int = 0                # root share exponent (0: every root)
     done: float = 0.0
     status: int = 0
     count: int | None = None
@@ -73,13 +77,14 @@ class GpuBackend:
         # the fixed side keeps planning free of host walks per request
         self.symmetry = symmetry
 
-    def plan(self, graph_id, pattern, pin_vertex=None):
+    def plan(self, graph_id, pattern, pin_vertex=None, share=0):
         from .api import Plan
-        key = (graph_id, pattern.k, pattern.arcs, pin_vertex)
+        key = (graph_id, pattern.k, pattern.arcs, pin_vertex, share)
         p = self.plans.get(key)
         if p is None:
             sym = "above" if self.symmetry else False
-            p = Plan(pattern, reduced=True, graph=self.graphs[graph_id], root_vertex=pin_vertex, symmetry=sym)
+            p = Plan(pattern, reduced=True, graph=self.graphs[graph_id], root_vertex=pin_vertex, symmetry=sym,
+                     root_share=share)
             self.plans[key] = p
         return p
 
@@ -95,9 +100,9 @@ class GpuBackend:
             raise XminerError(-1, lib().xm_last_error().decode())
         return int(ws) + 24 * len(plans)
 
-    def cost(self, graph_id, pattern, pin_vertex=None) -> float:
+    def cost(self, graph_id, pattern, pin_vertex=None, share=0) -> float:
         """The planner's work estimate for this request (cached with the plan)."""
-        p = self.plan(graph_id, pattern, pin_vertex)
+        p = self.plan(graph_id, pattern, pin_vertex, share)
         c = getattr(p, "_est_cost", None)
         if c is None:
             c = float(p.describe().get("est_cost", 0.0))
@@ -152,20 +157,24 @@ class Server:
         self.thread.start()
 
     # ---- client side
-    def submit(self, graph_id, pattern, deadline_s: float | None = None, pin=None, roots=None) -> Future:
+    def submit(self, graph_id, pattern, deadline_s: float | None = None, pin=None, roots=None,
+               share: int = 0) -> Future:
         """Queue a count of `pattern` on graph `graph_id`; pin = (v, x) anchors
         pattern vertex v at data node x; roots = (v, nodes) counts only the
-        embeddings that map v into the uint32 array `nodes`.  The future
-        gives (count, status)."""
-        if pin is not None and roots is not None:
-            raise ValueError("a request takes pin or roots, not both")
+        embeddings that map v into the uint32 array `nodes`; share = s > 0
+        counts only those whose start vertex maps to the root share s.  The
+        future gives (count, status)."""
+        if (pin is not None) + (roots is not None) + (int(share) != 0) > 1:
+            raise ValueError("a request takes one of pin, roots and share")
+        if not 0 <= int(share) <= 31:
+            raise ValueError("share must be in 0..31")
         now = time.perf_counter()
         f = Future()
         with self.lock:
             r = Request(self.next_id, graph_id, pattern, now,
                         now + deadline_s if deadline_s is not None else None, f,
                         pin=tuple(pin) if pin is not None else None,
-                        roots=(int(roots[0]), roots[1]) if roots is not None else None)
+                        roots=(int(roots[0]), roots[1]) if roots is not None else None, share=int(share))
             self.next_id += 1
             self.pending.append(r)
             self.lock.notify()
@@ -239,7 +248,7 @@ class Server:
             def est(r):
                 # a request that cannot be planned sorts last and fails below
                 try:
-                    return self.backend.cost(r.graph_id, r.pattern, self._vertex(r))
+                    return self.backend.cost(r.graph_id, r.pattern, self._vertex(r), share=r.share)
                 except Exception:
                     return float("inf")
             if sjf and now - head.submitted <= self.age_s:
@@ -267,7 +276,7 @@ class Server:
             plans, ok = [], []
             for r in batch:
                 try:
-                    plans.append(self.backend.plan(r.graph_id, r.pattern, self._vertex(r)))
+                    plans.append(self.backend.plan(r.graph_id, r.pattern, self._vertex(r), share=r.share))
                     ok.append(r)
                 except Exception as exc:
                     self._finish(r, self._code(exc), None)

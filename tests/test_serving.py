@@ -22,10 +22,10 @@ class FakeBackend:
         self.max_inflight = 0
         self.mu = threading.Lock()
 
-    def plan(self, graph_id, pattern, pin_vertex=None):
+    def plan(self, graph_id, pattern, pin_vertex=None, share=0):
         return (pattern, pin_vertex)
 
-    def cost(self, graph_id, pattern, pin_vertex=None):
+    def cost(self, graph_id, pattern, pin_vertex=None, share=0):
         return float(len(pattern.arcs))
 
     def footprint(self, graph_id, plans, node=None):
@@ -182,13 +182,13 @@ class FailingBackend(FakeBackend):
     2 or more plans) or launch (a c3 in the batch), like a library error or
     an out-of-memory during set-up would."""
 
-    def plan(self, graph_id, pattern, pin_vertex=None):
+    def plan(self, graph_id, pattern, pin_vertex=None, share=0):
         if pattern.k == 4:
             from paper_2404_11105_amd._lib import XminerError
             raise XminerError(-2, "pattern rejected")
         return super().plan(graph_id, pattern, pin_vertex)
 
-    def cost(self, graph_id, pattern, pin_vertex=None):
+    def cost(self, graph_id, pattern, pin_vertex=None, share=0):
         self.plan(graph_id, pattern, pin_vertex)
         return super().cost(graph_id, pattern, pin_vertex)
 
@@ -248,3 +248,49 @@ def test_root_subset_requests_batch_by_array_and_are_exact():
         assert s == 0 and c == oracle.count(gs["u"], p, roots=nodes, root_vertex=v)
     # the three requests on array a went out together at most in one launch each way
     assert srv.launches <= 4
+
+
+class ShareBackend(FakeBackend):
+    """Plans carry the request's root share; a plan starts at pattern vertex 0."""
+
+    def plan(self, graph_id, pattern, pin_vertex=None, share=0):
+        return (pattern, pin_vertex, share)
+
+    def launch(self, slot, graph_id, plans, node=None, roots=None):
+        import numpy as np
+        g = self.graphs[graph_id]
+        counts = []
+        for p, _, s in plans:
+            share = np.arange((1 << s) - 1, g.n, 1 << s, dtype=np.uint32)
+            counts.append(oracle.count(g, p, roots=share, root_vertex=0) if s else oracle.count(g, p))
+        with self.mu:
+            self.inflight += 1
+            self.launched.append((graph_id, len(plans)))
+        return {"t": time.perf_counter() + self.secs, "counts": counts, "done": False}
+
+
+def test_root_share_requests_reach_the_plan_and_batch_with_others():
+    """A request's root share is part of its plan: requests with different
+    shares on one graph go out in one launch, each with its own partial
+    count; a share with a pin or a root array, or past 31, is refused."""
+    gs = graphs()
+    be = ShareBackend(gs, secs_per_plan=0.001)
+    srv = Server(be, hbm_budget=10_000, slots=1, max_batch=8)
+    reqs = [(xmgen.named("ffl"), 0), (xmgen.named("ffl"), 2), (xmgen.named("c4"), 3), (xmgen.named("path3"), 1)]
+    with srv.lock:  # queue all four before the scheduler looks
+        futs = [srv.submit("u", p, share=s) for p, s in reqs]
+    res = [f.result(timeout=30) for f in futs]
+    srv.close()
+    import numpy as np
+    n = gs["u"].n
+    for (p, s), (c, st) in zip(reqs, res):
+        want = oracle.count(gs["u"], p, roots=np.arange((1 << s) - 1, n, 1 << s, dtype=np.uint32),
+                            root_vertex=0) if s else oracle.count(gs["u"], p)
+        assert st == 0 and c == want
+    assert be.launched == [("u", 4)]
+    srv = Server(be, hbm_budget=10_000)
+    for kw in ({"share": 2, "pin": (0, 1)}, {"share": 1, "roots": (0, np.arange(3, dtype=np.uint32))},
+               {"share": 32}):
+        with pytest.raises(ValueError):
+            srv.submit("u", xmgen.named("ffl"), **kw)
+    srv.close()
