@@ -156,15 +156,23 @@ def cpu_baseline(g, work, sample_desc):
             "value_1core": c1 / t1, "seconds_1core": round(t1, 4), "seconds_all_cores": round(tT, 4)}
 
 
+# hub roots of the oracle's sample, per pattern size: the first root of the
+# pattern's share at or above each of these degree ranks (R-MAT 22 in degree
+# order: rank 256 ~ degree 9,700, rank 1,024 ~ 9,400, rank 65,536 ~ 320).
+# A six-vertex pattern on a root of rank 65,536 took the oracle 68 s, so
+# six-vertex patterns get no hub root.
+SAMPLE_HUB_RANKS = {3: (256, 1024), 4: (256, 1024), 5: (65536,), 6: ()}
+
+
 def write_cpu_sample(n_patterns=16, per_pattern=128, chunks=8):
     """The oracle's sample of the batch workload (stored in
     workloads/batch256_cpu_sample.json; chosen from the stored batch without
-    running anything): every 16th pattern (four of each size) on 128 roots of
-    its own root share of degree rank [n/16, n/4) (all of them when the share
-    has fewer there; lists of a few to ten arcs: the bulk of the roots a
-    launch walks; two roots of degree rank in [n/64, n/16) already took the
-    oracle over a minute for a six-vertex pattern), in the generated ids,
-    split into 8 work items per pattern."""
+    running anything): every 16th pattern (four of each size), each on 128
+    seeded roots of its own root share of degree rank [n/16, n/4) (all of
+    them when the share has fewer there; lists of a few to ten arcs: the
+    bulk of the roots a launch walks) split into 8 work items, plus the hub
+    roots SAMPLE_HUB_RANKS names, one work item each; roots in the
+    generated ids."""
     import numpy as np
 
     from paper_2404_11105_amd import workloads
@@ -176,15 +184,23 @@ def write_cpu_sample(n_patterns=16, per_pattern=128, chunks=8):
     rng = np.random.default_rng(64)
     plans = workloads.batch_plans()
     work = []
+    n_hubs = 0
     for i in range(0, len(rec), len(rec) // n_patterns):
-        sh = workloads.share_roots(g.n, rec[i]["share"])
-        sh = sh[(sh >= g.n // 16) & (sh < g.n // 4)]
+        share = workloads.share_roots(g.n, rec[i]["share"])
+        sh = share[(share >= g.n // 16) & (share < g.n // 4)]
         roots = np.sort(old_of_new[rng.choice(sh, size=min(per_pattern, sh.size), replace=False)])
         rv = plans[i].describe()["root_vertex"]
         for c in np.array_split(roots, chunks):
             work.append([i, c.tolist(), rv])
+        for rank in SAMPLE_HUB_RANKS[rec[i]["k"]]:
+            hub = share[share >= rank]
+            if hub.size:
+                work.append([i, [int(old_of_new[hub[0]])], rv])
+                n_hubs += 1
     desc = (f"{n_patterns} of the 256 patterns (every 16th), up to {per_pattern} roots each from its root share "
-            f"at degree ranks [n/16, n/4), generated ids, {chunks} work items per pattern")
+            f"at degree ranks [n/16, n/4) in {chunks} work items, plus {n_hubs} hub roots (the first of the "
+            f"share at degree rank >= 256 and >= 1024 for 3-4-vertex patterns, >= 65536 for 5-vertex ones), "
+            f"one work item each; generated ids")
     out = {"description": desc, "work": work}
     with open(os.path.join(WL_DIR, "batch256_cpu_sample.json"), "w") as f:
         json.dump(out, f)
@@ -271,16 +287,26 @@ def bench_batch256(args):
     assert all(x == 0 for x in status), status
     extras = {}
     if not args.no_extras:
-        log("[batch] 256 plain launches")
-        ws = torch.empty(max(workspace_bytes(G, [p], **opts) for p in plans), dtype=torch.uint8, device="cuda")
-        plain = [Counter(G, [p], workspace=ws, **opts) for p in plans]
+        # 256 plain launches, each captured as its own HIP graph like the
+        # batched one, with the batch's tuned options and with the defaults
         steps_plain = max(1, args.steps // 4)
-        ms_p = timed_plain(plain, s, steps_plain, 1, progress=log)
-        plain_counts = [c.results()[0][0] for c in plain]
-        assert plain_counts == counts, "batched and plain counts differ"
+        ms_plain = {}
+        for label, o in (("batch_options", opts), ("default_options", {})):
+            log(f"[batch] 256 plain launches ({label})")
+            ws = torch.empty(max(workspace_bytes(G, [p], **o) for p in plans), dtype=torch.uint8, device="cuda")
+            plain = [Counter(G, [p], workspace=ws, **o) for p in plans]
+            for c in plain:
+                c.capture(s)
+            ms_plain[label] = timed_plain(plain, s, steps_plain, 1, progress=log)
+            plain_counts = [c.results()[0][0] for c in plain]
+            assert plain_counts == counts, "batched and plain counts differ"
+            del plain, ws
+        ms_p = min(ms_plain.values())
         extras.update({"plain_ms_per_step": round(ms_p, 3), "plain_steps": steps_plain,
-                       "batched_vs_plain_speedup": round(ms_p / ms_b, 3), "batched_equals_plain": True})
-        del plain, ws
+                       "plain_ms_by_options": {k: round(v, 3) for k, v in ms_plain.items()},
+                       "batched_vs_plain_speedup": round(ms_p / ms_b, 3), "batched_equals_plain": True,
+                       "plain_note": "each plain launch a HIP-graph replay; plain_ms_per_step is the faster "
+                                     "of the two option sets"})
     # issued bytes of the launch (host walk stored per plan set and row threshold)
     tr = load_json("batch256_traffic.json") or {}
     roofline, elements = None, None
@@ -530,8 +556,11 @@ def bench_listing(args):
 
 def bench_serve(args):
     """Continuous batching over 8 resident R-MAT graphs (scales 18-24, built
-    on the device); Poisson arrivals at two fixed rates set from the measured
-    capacity; p50/p99 latency and counts/s; results alone == in the mix."""
+    on the device, generated node order); each request draws a graph and a
+    pattern of 3-7 vertices from the serving pool, counted on the pattern's
+    root share of that graph; Poisson arrivals at two fixed rates set from
+    the measured capacity; p50/p99 latency and counts/s; results alone ==
+    in the mix."""
     import numpy as np
     import torch
 
@@ -547,7 +576,7 @@ def bench_serve(args):
         dg = xmgen.rmat_device(sc, seed=i)
         graphs[i] = Graph(dg)
     resident = sum(G.nbytes for G in graphs.values())
-    pool = workloads.batch_patterns()
+    pool = workloads.serve_pool()
     rng = np.random.default_rng(5)
 
     def draw(nreq):
@@ -561,7 +590,7 @@ def bench_serve(args):
     warm = draw(64)
     srv = Server(backend, budget, slots=4, max_batch=16)
     t0 = time.perf_counter()
-    futs = [srv.submit(gid, p) for gid, p in warm]
+    futs = [srv.submit(gid, p, share=sh) for gid, (p, sh) in warm]
     for f in futs:
         f.result()
     cap_rps = len(warm) / (time.perf_counter() - t0)
@@ -576,12 +605,12 @@ def bench_serve(args):
             srv = Server(backend, budget, slots=4, max_batch=16, policy=policy)
             futs = []
             t_next = time.perf_counter()
-            for (gid, p), gap in zip(reqs, gaps):
+            for (gid, (p, sh)), gap in zip(reqs, gaps):
                 t_next += gap
                 d = t_next - time.perf_counter()
                 if d > 0:
                     time.sleep(d)
-                futs.append(srv.submit(gid, p))
+                futs.append(srv.submit(gid, p, share=sh))
                 if len(futs) % 50 == 0:
                     log(f"[serve]   submitted {len(futs)}")
             res = []
@@ -599,7 +628,8 @@ def bench_serve(args):
     same = True
     for i in rng.choice(len(reqs), size=16, replace=False):
         srv = Server(backend, budget, slots=1, max_batch=1)
-        alone = srv.submit(*reqs[i]).result()
+        gid, (p, sh) = reqs[i]
+        alone = srv.submit(gid, p, share=sh).result()
         srv.close()
         same = same and alone == res[i]
     st = levels[-1][0]
@@ -610,6 +640,8 @@ def bench_serve(args):
         "data": "synthetic",
         "config": {"workload": "serve_rmat18-24x8", "graph_scales": scales,
                    "resident_bytes": resident, "pattern_pool": len(pool),
+                   "pool_sizes": {str(k): sum(1 for p, _ in pool if p.k == k) for k in range(3, 8)},
+                   "pool_shares": {str(sh): sum(1 for _, x in pool if x == sh) for sh in sorted({x for _, x in pool})},
                    "arrivals": "Poisson", "hbm_budget_bytes": budget, "slots": 4, "max_batch": 16,
                    "policies": ["fifo", "sjf"]},
         "capacity_requests_per_s": cap_rps,

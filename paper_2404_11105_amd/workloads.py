@@ -19,8 +19,14 @@ ones), and every later run rebuilds the same plans from it (reduced,
 symmetry-broken on the stored side, unit cover weights: no graph
 statistics, so the plans are the same on a host without a GPU).
 
+Serving pool (serve_pool): requests draw a pattern of 3-7 vertices with its
+root share, SERVE_PER_SIZE per size: the first entries of each size 3-6 of
+the batch, and 7-vertex patterns selected by the same rule with shares up to
+2^-20 (workloads/serve7.json, seeds from 700000).
+
     python -m paper_2404_11105_amd.workloads batch256 [out.json [resume.json]]  (on a GPU)
     python -m paper_2404_11105_amd.workloads batch256-tune [out.json]   (on a GPU)
+    python -m paper_2404_11105_amd.workloads serve7 [out.json [resume.json]]    (on a GPU)
     python -m paper_2404_11105_amd.workloads batch256-traffic           (host walk)
 """
 from __future__ import annotations
@@ -41,7 +47,10 @@ TOTAL_MS = 3000.0
 SHARES = (0, 2, 4, 6, 8, 10, 12, 14, 16)
 QUOTA = 64
 MAX_DRAWS = 1500
-SEED_BASE = {3: 300000, 4: 400000, 5: 500000, 6: 600000}
+SEED_BASE = {3: 300000, 4: 400000, 5: 500000, 6: 600000, 7: 700000}
+SERVE7_PATH = os.path.join(HERE, "workloads", "serve7.json")
+SERVE_PER_SIZE = 16
+SHARES_7 = SHARES + (18, 20)
 ROW_BYTES = 64 << 30    # dense-row budget of the scale-22 graph
 
 
@@ -60,6 +69,20 @@ def batch_patterns():
 def batch_shares():
     """Root share exponent of every accepted pattern (0: all roots)."""
     return [e["share"] for e in json.load(open(BATCH_PATH))["accepted"]]
+
+
+def serve_pool():
+    """(pattern, root share) of the serving requests, sizes 3-7: the first
+    SERVE_PER_SIZE batch entries of each size 3-6 and the selected 7-vertex
+    patterns (each with the share the same rule gave it)."""
+    import xmgen
+    acc = json.load(open(BATCH_PATH))["accepted"]
+    pool = []
+    for k in (3, 4, 5, 6):
+        pool += [(xmgen.random_pattern(k, e["seed"]), e["share"]) for e in acc if e["k"] == k][:SERVE_PER_SIZE]
+    if os.path.exists(SERVE7_PATH):
+        pool += [(xmgen.random_pattern(7, e["seed"]), e["share"]) for e in json.load(open(SERVE7_PATH))["accepted"]]
+    return pool
 
 
 def batch_plans():
@@ -118,6 +141,18 @@ def select_batch(out_path: str = BATCH_PATH, resume: str | None = None):
     """Draw and keep 256 patterns (see the module docstring); needs a GPU.
     The record is rewritten after every accepted pattern; `resume` (a
     record written earlier) continues its draws where they stopped."""
+    return _select(out_path, resume, (3, 4, 5, 6), QUOTA, SHARES, TOTAL_MS, None)
+
+
+def select_serve7(out_path: str = SERVE7_PATH, resume: str | None = None, budget_s: float = 900.0):
+    """The 7-vertex patterns of the serving pool: the same rule as the batch
+    (smallest share with a plain launch of at most CAP_MS on the scale-22
+    graph), shares up to 2^-20, SERVE_PER_SIZE of them or as many as
+    `budget_s` seconds of selection find; needs a GPU."""
+    return _select(out_path, resume, (7,), SERVE_PER_SIZE, SHARES_7, None, budget_s)
+
+
+def _select(out_path, resume, sizes, quota_k, shares, total_ms, budget_s):
     import torch
 
     import xmgen
@@ -128,7 +163,7 @@ def select_batch(out_path: str = BATCH_PATH, resume: str | None = None):
     G = Graph(g, order_by_degree=True, dense_rows=ROW_BYTES)
     s = torch.cuda.Stream()
     wd = Watchdog()
-    quota = {k: QUOTA for k in (3, 4, 5, 6)}
+    quota = {k: quota_k for k in sizes}
     accepted, total = [], 0.0
     rejected, draws = {k: 0 for k in quota}, {k: 0 for k in quota}
     spent = 0.0
@@ -147,7 +182,7 @@ def select_batch(out_path: str = BATCH_PATH, resume: str | None = None):
                         f"order, dense rows within {ROW_BYTES} bytes",
                "recipe": "random_pattern(k, seed); root share 2^-s: the smallest s in shares with a plain "
                          "launch of at most cap_ms on the MI355X",
-               "cap_ms": CAP_MS, "total_ms": TOTAL_MS, "shares": list(SHARES), "quota_per_size": QUOTA,
+               "cap_ms": CAP_MS, "total_ms": total_ms, "shares": list(shares), "quota_per_size": quota_k,
                "device": torch.cuda.get_device_name(0), "accepted": accepted, "plain_ms_total": round(total, 3),
                "rejected_per_k": rejected, "draws_per_k": draws,
                "selection_seconds": round(spent + time.time() - t0, 1)}
@@ -156,9 +191,11 @@ def select_batch(out_path: str = BATCH_PATH, resume: str | None = None):
             f.write("\n")
         return rec
 
-    while len(accepted) < 4 * QUOTA:
+    while len(accepted) < len(sizes) * quota_k:
+        if budget_s is not None and time.time() - t0 > budget_s:
+            break
         progressed = False
-        for k in (3, 4, 5, 6):
+        for k in sizes:
             if quota[k] == 0 or draws[k] >= MAX_DRAWS:
                 continue
             progressed = True
@@ -166,7 +203,7 @@ def select_batch(out_path: str = BATCH_PATH, resume: str | None = None):
             draws[k] += 1
             p = xmgen.random_pattern(k, seed)
             chosen = None
-            for sh in SHARES:
+            for sh in shares:
                 # the symmetry side that runs faster (both are exact)
                 best = None
                 for side in ("above", "below"):
@@ -179,7 +216,7 @@ def select_batch(out_path: str = BATCH_PATH, resume: str | None = None):
                 if best is not None and best[1] <= CAP_MS:
                     chosen = (sh, best[0], best[1])
                     break
-            if chosen is None or total + chosen[2] > TOTAL_MS:
+            if chosen is None or (total_ms is not None and total + chosen[2] > total_ms):
                 rejected[k] += 1
                 print(f"k={k} seed={seed} rejected t={time.time() - t0:.0f}s", flush=True)
                 continue
@@ -275,6 +312,10 @@ if __name__ == "__main__":
     if sys.argv[1:2] == ["batch256"]:
         r = select_batch(sys.argv[2] if len(sys.argv) > 2 else BATCH_PATH,
                          sys.argv[3] if len(sys.argv) > 3 else None)
+        print({k: v for k, v in r.items() if k != "accepted"})
+    elif sys.argv[1:2] == ["serve7"]:
+        r = select_serve7(sys.argv[2] if len(sys.argv) > 2 else SERVE7_PATH,
+                          sys.argv[3] if len(sys.argv) > 3 else None)
         print({k: v for k, v in r.items() if k != "accepted"})
     elif sys.argv[1:2] == ["batch256-traffic"]:
         print(batch_traffic(int(os.environ.get("XM_WALK_THREADS", "8")))["total"])

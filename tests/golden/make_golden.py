@@ -140,12 +140,22 @@ def rmat20_hubs():
                                "threads": THREADS, "results": res})
 
 
+SUBSET_HUB_RANK = {3: 0, 4: 256, 5: 4096, 6: 65536}
+SUBSET_OTHER_RANK = {3: 0, 4: 0, 5: 16384, 6: 262144}
+
+
 def batch_subsets(workers=None):
     """Root-subset parity for 16 of the 256 batch patterns on R-MAT scale 22:
     per size 3-6 the two with the longest plain launch and two seeded others.
     Each is counted on roots of its own root share (the roots the batch
-    counts): the two of largest degree in the share and 30 seeded others,
-    mapped back to the generated ids; one oracle count per root."""
+    counts), mapped back to the generated ids, one oracle count per root:
+    the two of largest degree in the share at or above degree rank
+    SUBSET_HUB_RANK[k] and 30 seeded others at or above SUBSET_OTHER_RANK[k]
+    (stored ids are degree ranks).  The floors keep the oracle within
+    minutes per pattern: a 4-vertex pattern on a rank-15 hub took it 12
+    minutes, a 5-vertex one on a rank-1,087 root 70 s, a 6-vertex one on a
+    rank-65,599 root 68 s.  The plan's start vertex (root_vertex) is the one
+    the batch's plan uses; it only selects which per-root count is stored."""
     from paper_2404_11105_amd import workloads
     rec = json.load(open(workloads.BATCH_PATH))
     acc = rec["accepted"]
@@ -161,18 +171,24 @@ def batch_subsets(workers=None):
     old_of_new = np.empty_like(new_of_old)
     old_of_new[new_of_old] = np.arange(g.n, dtype=np.uint32)
     pats = workloads.batch_patterns()
+    def stored_roots(i):
+        e = acc[i]
+        share = workloads.share_roots(g.n, e["share"])
+        hubs = share[share >= SUBSET_HUB_RANK[e["k"]]][:2]
+        others = np.setdiff1d(share[share >= SUBSET_OTHER_RANK[e["k"]]], hubs)
+        ri = np.random.default_rng(2560 + i)
+        return np.concatenate([hubs, np.sort(ri.choice(others, size=min(30, others.size), replace=False))])
+
     out = []
     path = os.path.join(HERE, "batch256_subsets.json")
-    if os.path.exists(path):  # continue a run that stopped: keep the patterns done
-        out = [r for r in json.load(open(path))["patterns"] if r["index"] in pick]
+    if os.path.exists(path):  # continue a run that stopped: keep the patterns done with these roots
+        out = [r for r in json.load(open(path))["patterns"]
+               if r["index"] in pick and r["stored_roots"] == stored_roots(r["index"]).tolist()]
     for i in pick:
         if any(r["index"] == i for r in out):
             continue
         e = acc[i]
-        share = workloads.share_roots(g.n, e["share"])
-        ri = np.random.default_rng(2560 + i)
-        stored = np.concatenate([share[:2], np.sort(ri.choice(share[2:], size=min(30, share.size - 2),
-                                                                replace=False))])
+        stored = stored_roots(i)
         roots = old_of_new[stored]
         from paper_2404_11105_amd.api import Plan
         rv = Plan(pats[i], reduced=True, symmetry=e["symmetry"], root_share=e["share"]).describe()["root_vertex"]
@@ -189,7 +205,7 @@ def batch_subsets(workers=None):
 
 SERVE_REQUESTS = [  # (R-MAT scale, seed, pattern): one request per serving graph
     (18, 0, "p7hub"), (19, 1, "rand6"), (20, 2, "c5chord"), (21, 3, "rand5"),
-    (22, 4, "bifan"), (23, 5, "rand4"), (24, 6, "ffl"), (24, 7, "c4"),
+    (22, 4, "bifan"), (23, 5, "rand4"), (24, 6, "ffl"), (24, 7, "c3"),
 ]
 
 
@@ -217,9 +233,17 @@ def serve_roots(g, seed, hubs: bool):
 def serve_scales():
     """Per-root oracle counts of one request per serving graph (R-MAT scales
     18-24, 16 arcs per node, seeds 0-7), start vertex 0, on 64 roots each
-    (with four hubs for the patterns of at most 4 vertices)."""
+    (with four hubs for the patterns of at most 4 vertices).  A 4-cycle on
+    the scale-24 graph ran over 40 minutes without finishing a root, so that
+    graph's second request is a 3-cycle."""
     out = []
+    path = os.path.join(HERE, "serve_scales.json")
+    if os.path.exists(path):  # continue a run that stopped: keep the requests done
+        out = [r for r in json.load(open(path))["requests"]
+               if (r["scale"], r["seed"], r["pattern"]) in SERVE_REQUESTS]
     for scale, seed, name in SERVE_REQUESTS:
+        if any((r["scale"], r["seed"], r["pattern"]) == (scale, seed, name) for r in out):
+            continue
         t = time.time()
         g = xmgen.rmat(scale, seed=seed)
         pat = serve_pattern(name)
