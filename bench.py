@@ -158,10 +158,10 @@ def cpu_baseline(g, work, sample_desc):
 
 # hub roots of the oracle's sample, per pattern size: the first root of the
 # pattern's share at or above each of these degree ranks (R-MAT 22 in degree
-# order: rank 256 ~ degree 9,700, rank 1,024 ~ 9,400, rank 65,536 ~ 320).
-# A six-vertex pattern on a root of rank 65,536 took the oracle 68 s, so
-# six-vertex patterns get no hub root.
-SAMPLE_HUB_RANKS = {3: (256, 1024), 4: (256, 1024), 5: (65536,), 6: ()}
+# order: rank 256 ~ degree 9,700, 1,024 ~ 9,400, 4,096 ~ 3,100, 16,384 ~
+# 1,000, 65,536 ~ 320).  A six-vertex pattern on a root of rank 65,536 took
+# the oracle 68 s, so six-vertex patterns get no hub root.
+SAMPLE_HUB_RANKS = {3: (256, 1024, 4096), 4: (256, 1024, 4096), 5: (16384, 65536), 6: ()}
 
 
 def write_cpu_sample(n_patterns=16, per_pattern=128, chunks=8):
@@ -199,8 +199,8 @@ def write_cpu_sample(n_patterns=16, per_pattern=128, chunks=8):
                 n_hubs += 1
     desc = (f"{n_patterns} of the 256 patterns (every 16th), up to {per_pattern} roots each from its root share "
             f"at degree ranks [n/16, n/4) in {chunks} work items, plus {n_hubs} hub roots (the first of the "
-            f"share at degree rank >= 256 and >= 1024 for 3-4-vertex patterns, >= 65536 for 5-vertex ones), "
-            f"one work item each; generated ids")
+            f"share at degree rank >= 256, >= 1024 and >= 4096 for 3-4-vertex patterns, >= 16384 and >= 65536 "
+            f"for 5-vertex ones), one work item each; generated ids")
     out = {"description": desc, "work": work}
     with open(os.path.join(WL_DIR, "batch256_cpu_sample.json"), "w") as f:
         json.dump(out, f)
