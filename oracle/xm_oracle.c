@@ -36,6 +36,10 @@
  * counted), up to a capacity; the total is always exact.
  *
  * The oracle reads only the out-CSR and builds its own sorted in-lists.
+ *
+ * Parity unpinned: the 128-bit accumulation of totals above 2^64 (no
+ * enumeration reaches such a total in reasonable time, and no stored value
+ * depends on it; the GPU's 128-bit path is pinned by a closed form instead).
  */
 #include <stdint.h>
 #include <stdlib.h>
