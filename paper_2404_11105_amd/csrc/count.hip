@@ -1201,16 +1201,23 @@ __global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_ker
             // interleave plans so that all of them start on the low (hub) ids
             set_plan(uni(item % a.n_plans));
             const uint32_t ci = item / a.n_plans;
+            // without a root list, a plan on a root share counts the ids
+            // (j + 1) 2^s - 1 only: its chunks run over j, so that every lane
+            // of a chunk gets a root of the share (n >> s of them)
+            const uint32_t sh = C.P->root_share;
+            const bool compact = a.roots == nullptr && sh > 0;
+            const uint64_t n_p = compact ? ((uint64_t)a.n_src >> sh) : (uint64_t)a.n_src;
+            const uint64_t cpp = compact ? (n_p + a.chunk - 1) / a.chunk : chunks_per_plan;
             // chunk ci takes the roots ci, ci + chunks, ci + 2 chunks, ...: long
             // lists cluster at low ids on power-law generators, and striding
             // spreads them over many tasks
-            const uint64_t idx64 = (uint64_t)ci + (uint64_t)C.lane * chunks_per_plan;
-            const uint32_t idx = (uint32_t)(idx64 < a.n_src ? idx64 : a.n_src);
-            bool ok = C.lane < a.chunk && idx64 < a.n_src;
+            const uint64_t idx64 = (uint64_t)ci + (uint64_t)C.lane * cpp;
+            const uint32_t idx = (uint32_t)(idx64 < n_p ? idx64 : n_p);
+            bool ok = C.lane < a.chunk && ci < cpp && idx64 < n_p;
             uint32_t r = 0;
             if (ok) {
-                r = a.roots ? a.roots[idx] : idx;
-                ok = r < a.g.n && in_root_share(r, C.P->root_share);
+                r = compact ? (uint32_t)(((idx64 + 1) << sh) - 1) : (a.roots ? a.roots[idx] : idx);
+                ok = r < a.g.n && in_root_share(r, sh);
             }
             if (ok) {
                 uint2 d = a.g.deg[r];

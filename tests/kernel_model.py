@@ -312,11 +312,13 @@ class Model:
         for r, lo, hi in items:
             F0["node"][0], F0["parent"][0], F0["aux"][0] = r, lo, hi
             self.explore(1)
-        n_chunks = -(-g.n // self.chunk)
+        # a plan on a root share chunks the share's ids (j + 1) 2^s - 1 only
+        ids = range((1 << share) - 1, g.n, 1 << share)
+        n_chunks = -(-len(ids) // self.chunk)
         for c0 in range(n_chunks):
             n0 = 0
             # chunk c0 takes the roots c0, c0 + n_chunks, ... (strided)
-            for r in range(c0, g.n, n_chunks)[: self.chunk]:
+            for r in ids[c0::n_chunks][: self.chunk]:
                 if not in_share(r):
                     continue
                 do, di = self.deg(r)

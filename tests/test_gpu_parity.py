@@ -351,6 +351,43 @@ def test_symmetry_rejects_root_subsets_and_listing(xa):
     assert got == [oracle.count(g, xmgen.named("ffl"))] and st == [0]
 
 
+def test_root_share_counts_vs_oracle(xa):
+    """Plans on a root share (XM_PLAN_ROOT_SHARE: only stored ids r with
+    r mod 2^s = 2^s - 1 as images of the start vertex) against the oracle on
+    the same roots, in generated and in degree order, reduced and unreduced,
+    with and without symmetry breaking (then only automorphisms fixing the
+    start vertex), batched, with chunks that leave a share's last chunk part
+    full."""
+    pats = [xmgen.named(n) for n in ["ffl", "c3", "bifan", "c4", "tt4p", "c5chord"]]
+    pats += [xmgen.random_pattern(5, 51), xmgen.random_pattern(6, 61)]
+    g = xmgen.rmat(8, seed=3)
+    memo = {}
+
+    def oracle_count(i, roots, rv):
+        key = (i, roots.tobytes(), rv)
+        if key not in memo:
+            memo[key] = oracle.count(g, pats[i], roots=roots, root_vertex=rv, mode="B")
+        return memo[key]
+    for order in (False, True):
+        G = xa.Graph(g, order_by_degree=order)
+        old_of_new = np.arange(g.n, dtype=np.uint32)
+        if order:
+            old_of_new[G.node_order()] = np.arange(g.n, dtype=np.uint32)
+        for share in (2, 3, 5):
+            stored = np.arange((1 << share) - 1, g.n, 1 << share, dtype=np.uint32)
+            banner(f"root share {share} ({stored.size} roots), degree order {order}")
+            for reduced in (True, False):
+                for symmetry in (False, True):
+                    plans = [xa.Plan(p, reduced=reduced, graph=G, symmetry=symmetry, root_share=share)
+                             for p in pats]
+                    want = [oracle_count(i, np.sort(old_of_new[stored]), pl.root_vertex)
+                            for i, pl in enumerate(plans)]
+                    for chunk in (0, 1, 3):
+                        c = xa.Counter(G, plans, chunk=chunk)
+                        c.run()
+                        assert c.results() == (want, [0] * len(pats)), (order, share, reduced, symmetry, chunk)
+
+
 def test_degree_order_keeps_counts(xa):
     """A graph stored with its nodes renumbered by decreasing degree gives the
     oracle's counts with and without symmetry breaking (either direction),
