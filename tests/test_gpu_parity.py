@@ -388,6 +388,21 @@ def test_root_share_counts_vs_oracle(xa):
                         assert c.results() == (want, [0] * len(pats)), (order, share, reduced, symmetry, chunk)
 
 
+def test_root_items_past_32_bits_are_refused(xa):
+    """Root items (plan, chunk) are numbered in 32 bits: a launch whose
+    ceil(n / chunk) x n_plans reaches 2^32 is refused before anything runs
+    (2^22 nodes, 1,024 plans, chunk 1), one with half as many items is
+    accepted."""
+    from paper_2404_11105_amd._lib import XminerError
+    banner("root items: 2^22 nodes x 1024 plans at chunk 1 and 2")
+    g = xmgen.uniform_digraph(1 << 22, 64, 1)
+    G = xa.Graph(g, dense_rows=0)
+    plans = [xa.Plan(xmgen.named("ffl"), graph=G)] * 1024
+    with pytest.raises(XminerError, match="root items"):
+        xa.Counter(G, plans, chunk=1)
+    xa.Counter(G, plans, chunk=2)
+
+
 def test_degree_order_keeps_counts(xa):
     """A graph stored with its nodes renumbered by decreasing degree gives the
     oracle's counts with and without symmetry breaking (either direction),
