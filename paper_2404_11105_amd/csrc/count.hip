@@ -337,6 +337,7 @@ __device__ uint32_t phase_a(Ctx& C, const LK& D, uint32_t lv, uint32_t p, bool p
     if (!fetched) {
         // the shortest list is the base; the others are probed
         uint32_t best = kSkip, bc = 0, bo = 0;
+        uint32_t dbest = kSkip, dc = 0, dof = 0, dlv = 0;  // shortest list at the deepest bound level
         for (uint32_t c = 0; c < D.n_cons; c++) {
             const uint32_t nd = C.s.bound[D.lvl(c) * 64 + lane];
             const uint32_t* off = off_of(g, D.dir(c));
@@ -346,6 +347,19 @@ __device__ uint32_t phase_a(Ctx& C, const LK& D, uint32_t lv, uint32_t p, bool p
                 bc = c;
                 bo = o;
             }
+            if (D.lvl(c) > dlv || (D.lvl(c) == dlv && l < dbest)) {
+                dlv = D.lvl(c);
+                dbest = l;
+                dc = c;
+                dof = o;
+            }
+        }
+        // the first level keeps the shortest: root sub-ranges index into it
+        if (kFreshBaseRatio && (IS_SIG || lv >= 2) && D.lvl(bc) < dlv &&
+            (uint64_t)dbest <= (uint64_t)kFreshBaseRatio * best) {
+            best = dbest;
+            bc = dc;
+            bo = dof;
         }
         for (uint32_t c = 0; c < D.n_cons; c++) {
             if (c == bc) continue;

@@ -112,7 +112,7 @@ struct Walker {
     // search, issued model); the merge model also counts only the parts of
     // the probe lists on that side, which is what a merge would read.
     void lists(const LevelDesc& D, const uint32_t*& base, uint32_t& blen, const uint32_t* probe[kMaxCons],
-               uint32_t plen[kMaxCons], int& np) {
+               uint32_t plen[kMaxCons], int& np, bool fresh_ok) {
         np = 0;
         if (D.reuse != kNoReuse) {
             base = cand[D.reuse].data();
@@ -124,13 +124,19 @@ struct Walker {
                 }
             w.offset_pairs += (uint64_t)np;
         } else {
-            int bc = 0;
+            int bc = 0, dc = 0;
             const uint32_t* a[kMaxCons];
             uint32_t l[kMaxCons];
             for (int c = 0; c < D.n_cons; c++) {
                 list(phi[D.cons_lvl[c]], D.cons_dir[c], a[c], l[c]);
                 if (l[c] < l[bc]) bc = c;
+                if (D.cons_lvl[c] > D.cons_lvl[dc] || (D.cons_lvl[c] == D.cons_lvl[dc] && l[c] < l[dc])) dc = c;
             }
+            // the kernel's choice: the deepest bound vertex's list when it is
+            // within kFreshBaseRatio of the shortest (not on the first level)
+            if (kFreshBaseRatio && fresh_ok && D.cons_lvl[bc] < D.cons_lvl[dc] &&
+                (uint64_t)l[dc] <= (uint64_t)kFreshBaseRatio * l[bc])
+                bc = dc;
             base = a[bc];
             blen = l[bc];
             for (int c = 0; c < D.n_cons; c++)
@@ -201,7 +207,7 @@ struct Walker {
         const uint32_t* probe_l[kMaxCons];
         uint32_t plen[kMaxCons];
         int np;
-        lists(L, base, blen, probe_l, plen, np);
+        lists(L, base, blen, probe_l, plen, np, true);
         for (uint32_t i = 0; i < blen; i++) test(L, 0u, nb, probe_l, plen, np, base[i]);
         for (uint32_t b = 0; b < nb; b++) {
             if (!((L.inj >> b) & 1u)) continue;
@@ -262,7 +268,7 @@ struct Walker {
         int np;
         // the parent's chain: node and parent per bound level
         w.chain_words += 2ull * lv;
-        lists(D, base, blen, probe_l, plen, np);
+        lists(D, base, blen, probe_l, plen, np, lv >= 2);
         std::vector<uint32_t>& out = cand[lv];
         out.clear();
         for (uint32_t i = 0; i < blen; i++) {

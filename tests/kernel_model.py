@@ -14,6 +14,10 @@ modelled.
 from __future__ import annotations
 
 SKIP = 0xFFFFFFFF
+# the kernel's base choice below the first level (kFreshBaseRatio in
+# kernels.h): the deepest bound vertex's list when at most this many times
+# longer than the shortest
+FRESH_BASE_RATIO = 2
 
 
 class Model:
@@ -89,6 +93,11 @@ class Model:
                 self.reads.add((tag, c, D["reuse"] >= 0))
             lists = [(d,) + self.lst(bound[j], d) + (bound[j],) for j, d in D["cons"]]
             bi = min(range(len(lists)), key=lambda i: (lists[i][2], i))
+            if FRESH_BASE_RATIO and (is_sig or lv >= 2):
+                # the deepest bound vertex's list when within the ratio of the shortest
+                dc = min(range(len(lists)), key=lambda i: (-D["cons"][i][0], lists[i][2], i))
+                if D["cons"][bi][0] < D["cons"][dc][0] and lists[dc][2] <= FRESH_BASE_RATIO * lists[bi][2]:
+                    bi = dc
             meta["kind"] = lists[bi][0]
             meta["off"] = lists[bi][1]
             ln = lists[bi][2]
