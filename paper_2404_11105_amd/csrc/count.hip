@@ -1046,12 +1046,12 @@ __device__ void explore(Ctx& C, uint32_t n0, uint32_t start) {
     }
 }
 
-#ifndef XM_MIN_BLOCKS_PER_CU
-#define XM_MIN_BLOCKS_PER_CU 8  // resident blocks per CU the register allocator must allow (8 waves per SIMD)
-#endif
-
-template <bool NONLIN>
-__global__ void __launch_bounds__(kBlockThreads, XM_MIN_BLOCKS_PER_CU) count_kernel(KArgs a) {
+// Two register budgets.  MINB resident blocks per CU: 8 (8 waves per SIMD,
+// 64 VGPRs, some state spilled to scratch) for launches of more than
+// kRoomyWavesPerCu waves per CU, and kRoomyBlocksPerCu (3 waves per SIMD,
+// the whole kernel in registers) for launches of at most that many.
+template <bool NONLIN, int MINB>
+__global__ void __launch_bounds__(kBlockThreads, MINB) count_kernel(KArgs a) {
     extern __shared__ uint32_t smem[];
     Ctx C;
     C.a = &a;
@@ -1367,9 +1367,9 @@ int count_blocks_per_cu(bool nonlin, size_t lds_bytes) {
     int nb = 0;
     hipError_t e;
     if (nonlin)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, count_kernel<true>, kBlockThreads, lds_bytes);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, count_kernel<true, 8>, kBlockThreads, lds_bytes);
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, count_kernel<false>, kBlockThreads, lds_bytes);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, count_kernel<false, 8>, kBlockThreads, lds_bytes);
     return e == hipSuccess ? nb : 0;
 }
 
@@ -1412,10 +1412,16 @@ hipError_t launch_count(const InitArgs* inits, int n_inits, const KArgs& a, uint
         hipError_t e = hipEventRecord(ev_start, stream);
         if (e != hipSuccess) return e;
     }
-    if (a.nonlinear)
-        hipLaunchKernelGGL(count_kernel<true>, dim3(n_blocks), dim3(kBlockThreads), lds, stream, a);
+    // the whole kernel in registers when the launch asks for few enough waves
+    const bool roomy = n_blocks <= (uint64_t)a.n_cu * kRoomyBlocksPerCu;
+    if (a.nonlinear && roomy)
+        hipLaunchKernelGGL((count_kernel<true, kRoomyBlocksPerCu>), dim3(n_blocks), dim3(kBlockThreads), lds, stream, a);
+    else if (a.nonlinear)
+        hipLaunchKernelGGL((count_kernel<true, 8>), dim3(n_blocks), dim3(kBlockThreads), lds, stream, a);
+    else if (roomy)
+        hipLaunchKernelGGL((count_kernel<false, kRoomyBlocksPerCu>), dim3(n_blocks), dim3(kBlockThreads), lds, stream, a);
     else
-        hipLaunchKernelGGL(count_kernel<false>, dim3(n_blocks), dim3(kBlockThreads), lds, stream, a);
+        hipLaunchKernelGGL((count_kernel<false, 8>), dim3(n_blocks), dim3(kBlockThreads), lds, stream, a);
     if (ev_stop) {
         hipError_t e = hipEventRecord(ev_stop, stream);
         if (e != hipSuccess) return e;

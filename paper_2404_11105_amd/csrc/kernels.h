@@ -108,6 +108,7 @@ struct KArgs {
     uint32_t lds_rows;          // bound / ancestor rows (largest enumerated depth)
     uint32_t maxc;              // largest constraint count over plans and signatures
     uint32_t nonlinear;         // some plan counts a leaf group of several vertices
+    uint32_t n_cu;              // compute units of the device (picks the register budget)
     uint32_t merge_min;         // cooperative merge thresholds
     uint32_t merge_ratio;
     uint32_t wave_words;        // scratch words per wave
@@ -135,6 +136,9 @@ struct InitArgs {
 // entries: the task size shrinks as the list grows, because each first-level
 // candidate of a long list usually carries a long list below it.
 constexpr uint32_t kMaxPieces = 4096;  // sub-range tasks per root and plan, at most
+// launches of at most this many resident blocks per CU use the count kernel
+// compiled for that occupancy, which keeps all its state in registers
+constexpr int kRoomyBlocksPerCu = 3;
 
 // The base list of a level below the first (and of a leaf pass): the
 // shortest constraint list, except that when the shortest belongs to an

@@ -372,6 +372,7 @@ int enqueue_count(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const*
     a.merge_min = L.merge_min;
     a.merge_ratio = (o && o->merge_ratio) ? o->merge_ratio : xm::kMergeRatio;
     a.nonlinear = L.nonlinear ? 1u : 0u;
+    a.n_cu = (uint32_t)g->n_cu;
     a.wave_words = L.wave_words;
     a.scratch = reinterpret_cast<uint32_t*>(base + L.off_scratch);
     a.counts = reinterpret_cast<unsigned long long*>(counts);

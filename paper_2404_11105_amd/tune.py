@@ -32,7 +32,7 @@ SPACE = [
     ("split_work", [4096, 16384, 65536]),
     ("split", [64, 128, 512]),
     ("chunk", [0, 1, 4, 16, 64]),
-    ("waves_per_cu", [0, 16, 32]),
+    ("waves_per_cu", [0, 12, 16, 32]),
     ("merge_min", [0xFFFFFFFF, 64]),
 ]
 DEFAULTS = dict(split_work=4096, split=64, chunk=0, waves_per_cu=0, merge_min=0xFFFFFFFF)
