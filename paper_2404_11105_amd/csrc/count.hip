@@ -1048,7 +1048,7 @@ __device__ void explore(Ctx& C, uint32_t n0, uint32_t start) {
 
 // Two register budgets.  MINB resident blocks per CU: 8 (8 waves per SIMD,
 // 64 VGPRs, some state spilled to scratch) for launches of more than
-// kRoomyWavesPerCu waves per CU, and kRoomyBlocksPerCu (3 waves per SIMD,
+// kRoomyBlocksPerCu blocks per CU, and kRoomyBlocksPerCu (3 waves per SIMD,
 // the whole kernel in registers) for launches of at most that many.
 template <bool NONLIN, int MINB>
 __global__ void __launch_bounds__(kBlockThreads, MINB) count_kernel(KArgs a) {
@@ -1076,10 +1076,10 @@ __global__ void __launch_bounds__(kBlockThreads, MINB) count_kernel(KArgs a) {
     const uint64_t total_chunks = chunks_per_plan * a.n_plans;
     Lvl F0 = lvl_arrays(C.scr, a.cap, 0);
     uint32_t taken = 0;
-    // root items come from kQueues interleaved cursors (cursor q: items q,
-    // q + kQueues, ...), so the grabs spread over several words and every
-    // cursor still walks the items in order; a wave starts at its home
-    // cursor and moves on once one runs dry
+    // root items (item = chunk index x n_plans + plan) come from kQueues
+    // cursors, so the grabs spread over several words and every cursor still
+    // walks its items in order; a wave starts at its home cursor (its XCD's)
+    // and moves on once one runs dry
     uint32_t rq = home, rtried = 0;
     // a wave counts as active from its first task until the queues run dry
     // (and again while it runs a donated task), not per task
@@ -1116,7 +1116,18 @@ __global__ void __launch_bounds__(kBlockThreads, MINB) count_kernel(KArgs a) {
             }
             while (!stop && kind == 2 && rtried < kQueues) {
                 const uint32_t c = atomicAdd(&a.ctl[kCtlRootCursor0 + 32 * rq], 1u);
-                const uint64_t it = (uint64_t)rq + (uint64_t)kQueues * c;
+                uint64_t it;
+                if (a.n_plans > kQueues) {
+                    // chunk-major: cursor q walks the chunk indices q, q + kQueues, ...
+                    // with all plans of one index in a row, so the plans whose
+                    // chunks hold the same roots run on one XCD and share its L2
+                    const uint64_t ci = (uint64_t)rq + (uint64_t)kQueues * (c / a.n_plans);
+                    it = ci * a.n_plans + c % a.n_plans;
+                } else {
+                    // plan-major: with few plans, cursor q keeps to the plans q mod
+                    // n_plans, so a wave's counts stay in its lanes between tasks
+                    it = (uint64_t)rq + (uint64_t)kQueues * c;
+                }
                 if (it < total_chunks) {
                     kind = 1;
                     item = (uint32_t)it;
