@@ -364,7 +364,7 @@ def bench_batch256(args):
 
 
 def extra_rmat16(args):
-    """Config 2 beside the line: R-MAT scale 16, four motifs, reduced
+    """Beside the line: R-MAT scale 16, four motifs, reduced
     symmetry-broken plans in one batched launch; plain launches; unreduced
     plans; counts checked against the stored oracle values."""
     import torch
@@ -399,7 +399,7 @@ def extra_rmat16(args):
 
 
 def extra_rmat20(args):
-    """Config 3 beside the line: R-MAT scale 20, transitive tournament on 4
+    """Beside the line: R-MAT scale 20, transitive tournament on 4
     vertices plus a pendant in-arc (every root) and the 5-cycle with a chord
     (root share 1/64), each as the reduced plan (leaf groups counted by
     product, included arcs taken from the including arc's candidates)

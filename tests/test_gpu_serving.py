@@ -142,7 +142,7 @@ def test_rmat20_hub_roots_per_root_parity(xa):
 
 
 def test_serving_one_request_per_graph_scale_vs_oracle(xa):
-    """Config 5's graphs (R-MAT scales 18-24 and 24, seeds 0-7, all resident
+    """The serving graphs (R-MAT scales 18-24 and 24, seeds 0-7, all resident
     at once): one root-subset request per graph through the serving loop,
     each count equal to the oracle's sum over its 64 roots (for the patterns
     of at most 4 vertices, 4 hubs of degree rank 1000-1003 among them)."""
@@ -246,7 +246,7 @@ def test_side_stream_launch_waits_for_setup(xa):
 
 
 def test_batch256_root_subset_parity(xa):
-    """Config 4's graph (R-MAT scale 22) and 16 of its 256 patterns (per size
+    """The batch graph (R-MAT scale 22) and 16 of its 256 patterns (per size
     3-6 the two with the longest plain launch and two others): each counted
     one root at a time on 32 roots of its own root share -- the two of
     largest degree in the share above a degree-rank floor per pattern size
