@@ -182,8 +182,14 @@ int make_layout(const xm_graph_t* g, uint32_t n_plans, const xm_plan_t* const* p
     L.merge_min = (o && o->merge_min) ? o->merge_min : xm::kMergeMin;
     L.lds_words = xm::lds_words_for(L.e_max, L.maxc, L.nonlinear, L.merge_min != 0xFFFFFFFFu);
     if (L.waves_per_cu == 0) {
-        // as many waves as can be resident at once: the kernel is persistent
+        // as many waves as can be resident at once: the kernel is persistent.
+        // When LDS leaves room for fewer than 6 blocks of the 64-VGPR kernel,
+        // its extra occupancy does not pay for its spills: take the kernel
+        // that keeps everything in registers at its kRoomyBlocksPerCu blocks
+        // (measured: 256 plans on R-MAT 22 1,340 ms at 3 blocks against
+        // 1,374 ms at 4; TT4 + pendant on R-MAT 20 2,199 ms against 2,787 ms)
         int bpc = xm::count_blocks_per_cu(L.nonlinear, (size_t)L.lds_words * 4 * xm::kWavesPerBlock);
+        if (bpc < 6) bpc = std::min(bpc, xm::kRoomyBlocksPerCu);
         L.waves_per_cu = (uint32_t)std::max(1, std::min(bpc, 8)) * xm::kWavesPerBlock;
     }
     L.n_waves = (uint32_t)g->n_cu * L.waves_per_cu;
