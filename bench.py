@@ -38,6 +38,7 @@ sys.path.insert(0, ROOT)
 METRIC = ("embeddings counted/sec + adjacency elems intersected/s (HBM GB/s %), "
           "batched vs plain")
 HBM_PEAK_GBPS = 8000.0
+SJF_AGE_S = 0.25  # serving: a request waiting longer than this goes first under sjf
 N_CU, CLOCK_HZ = 256, 2.4e9   # MI355X: VALU issue capacity = one wave64 instruction per CU per cycle
 PATTERNS = ["ffl", "c3", "bifan", "c4"]
 C5CHORD_SHARE = 6             # scale-20 extra: the 5-cycle with a chord on 1/64 of the roots
@@ -612,7 +613,7 @@ def bench_serve(args):
         gaps = rng.exponential(1.0 / qps, size=len(reqs))
         for policy in ("fifo", "sjf"):
             log(f"[serve] {len(reqs)} requests at {qps:.1f}/s, policy {policy}")
-            srv = Server(backend, budget, slots=4, max_batch=16, policy=policy)
+            srv = Server(backend, budget, slots=4, max_batch=16, policy=policy, age_s=SJF_AGE_S)
             futs = []
             t_next = time.perf_counter()
             for (gid, (p, sh)), gap in zip(reqs, gaps):
@@ -653,6 +654,7 @@ def bench_serve(args):
                    "pool_sizes": {str(k): sum(1 for p, _ in pool if p.k == k) for k in range(3, 8)},
                    "pool_shares": {str(sh): sum(1 for _, x in pool if x == sh) for sh in sorted({x for _, x in pool})},
                    "arrivals": "Poisson", "hbm_budget_bytes": budget, "slots": 4, "max_batch": 16,
+                   "sjf_age_s": SJF_AGE_S,
                    "policies": ["fifo", "sjf"]},
         "capacity_requests_per_s": cap_rps,
         "capacity_draws_requests_per_s": [round(c, 1) for c in caps],

@@ -273,8 +273,13 @@ typedef struct xm_count_opts {
                                root, 8 x split (at most cap) and 16 x split_work */
     uint32_t cap;           /* per-level candidate buffer entries (default 4096,
                                at least split) */
-    uint32_t waves_per_cu;  /* resident waves per compute unit (default: as many
-                               as the kernel's registers and LDS allow, at most 32) */
+    uint32_t waves_per_cu;  /* resident waves per compute unit, 4..32 (default:
+                               as many as LDS allows, at most 32; when that is
+                               fewer than 24, 12 or as many as LDS allows).
+                               Launches of at most 12 waves per CU run a build
+                               of the count kernel that keeps all its state in
+                               registers; larger ones a build limited to 64
+                               VGPRs that spills some of it. */
     /* root subset: device array of n_roots node ids (< n, distinct); when
        non-NULL only these nodes are tried as images of the plan's start
        vertex (xm_plan_root_vertex).  Counts are then exact partial sums.
