@@ -1278,8 +1278,10 @@ __global__ void split_kernel(KArgs a) {
     const uint64_t total = (uint64_t)nsrc * a.n_plans;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
          i += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t pi = (uint32_t)(i / nsrc);
-        uint32_t h = (uint32_t)(i % nsrc);
+        // root-major: the tasks of all plans on one hub are pushed together,
+        // so the waves of its XCD work on that hub's lists side by side
+        const uint32_t pi = (uint32_t)(i % a.n_plans);
+        const uint32_t h = (uint32_t)(i / a.n_plans);
         const PlanDesc* P = a.plans + pi;
         if (P->e < 2) continue;
         uint32_t r = a.roots ? a.roots[h] : a.hubs[h];
