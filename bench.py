@@ -416,7 +416,7 @@ def extra_rmat20(args):
     G = Graph(g, order_by_degree=True)
     s = torch.cuda.Stream()
     wd = Watchdog()
-    limit_s = 60.0
+    limit_s = float(getattr(args, "rmat20_limit_s", 60.0))
     out = {"cancel_after_s": limit_s}
     # the 5-cycle with a chord has ~10^14 embeddings and does not finish
     # within the limit on every root: it is counted on a root share
@@ -677,6 +677,8 @@ def main():
                     choices=["batch256", "rmat16", "rmat20", "serve", "fraction", "listing"],
                     help="batch256: the contract line (default); the others print their own JSON line")
     ap.add_argument("--requests", type=int, default=150, help="serve: requests per load level and policy")
+    ap.add_argument("--rmat20-limit-s", type=float, default=60.0,
+                    help="R-MAT 20 reduced vs unreduced: cancel a launch after this many seconds")
     ap.add_argument("--write-cpu-sample", action="store_true",
                     help="write the oracle's sample of the batch workload and time it (host only)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
